@@ -1,0 +1,23 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _host_libs():
+    """Build the host-side C libraries (input generator, oracle) if absent."""
+    import oracle
+    import synth
+    if not os.path.exists(synth._LIB_PATH):
+        synth.build()
+    if not os.path.exists(oracle._LIB_PATH):
+        oracle.build()
