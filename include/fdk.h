@@ -1,0 +1,158 @@
+/*
+ * fdk.h - C ABI of the MI355X (gfx950) cone-beam backprojection library.
+ *
+ * The library computes the voxel-driven backprojection step of the Feldkamp
+ * (FDK) reconstruction: for every voxel and every projection i, the 3x4
+ * matrix P_i maps the voxel centre to (u w, v w, w); the filtered projection
+ * is sampled bilinearly at (u, v) and fx / w^2 is added to the voxel
+ * (paper, Section 3.1, Listing 1, and the three parts of Section 3.2).
+ *
+ * Conventions shared by every entry point:
+ *   volume     device float, N*N*N, voxel (x, y, z) at volume[(z*N + y)*N + x];
+ *              its centre is origin + voxel_size * (x, y, z) in mm.
+ *   proj_stack device, n_views*H*W, pixel (j, k) of view i at
+ *              [(i*H + k)*W + j]; the pixel's centre is at u = j, v = k.
+ *   P_mats     host double, n_views*12, row-major 3x4 per view mapping
+ *              homogeneous world mm (x, y, z, 1) to (u w, v w, w).
+ *              Read during the call only (folded and rounded to FP32 on the
+ *              host; the library keeps no pointer to it).
+ *   origin     host float[3].
+ *   stream     a hipStream_t passed as void*; NULL is the null stream.
+ * Semantics:
+ *   - The backprojection ACCUMULATES into the volume (+=); zero it first for
+ *     a fresh reconstruction.  Views may be streamed over several calls.
+ *   - Taps outside the detector read 0; the cast of u, v to a pixel index is
+ *     floor; a voxel with w <= 0 receives nothing from that view.
+ *   - Calls are asynchronous: they return once the work is enqueued on
+ *     `stream`.  The caller keeps every device buffer alive and unmodified
+ *     until the stream has passed the call.  Two calls that write the same
+ *     output must be ordered on one stream (or by events) by the caller.
+ *   - The library never frees or retains caller memory.  It owns one
+ *     staging buffer per device (zero-padded copies of a batch of views),
+ *     grown on demand and released by fdk_release().  Calls on different
+ *     streams that share it are ordered by the library with events.
+ * Errors: every entry point returns FDK_OK (0) or a negative code, and
+ * fdk_last_error() describes the last failure of the calling thread.
+ * Arguments are validated before anything is enqueued; a rejected call has
+ * no effect.  Non-finite data values propagate unchecked.
+ */
+#ifndef FDK_H
+#define FDK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDK_OK 0
+#define FDK_ERR_INVALID_ARG (-1) /* null pointer, bad size, non-finite geometry */
+#define FDK_ERR_HIP (-2)         /* a HIP runtime call or kernel launch failed */
+#define FDK_ERR_UNSUPPORTED (-3) /* valid request the library cannot serve */
+
+/* Projection storage types for fdk_backproject_ex. */
+#define FDK_DTYPE_F32 0
+#define FDK_DTYPE_F16 1
+#define FDK_DTYPE_BF16 2
+
+/* Kernel variants for fdk_backproject_ex (flags). */
+#define FDK_KERNEL_FUSED 0 /* several views fused per pass, z-line per thread */
+#define FDK_KERNEL_PLAIN 1 /* one thread per voxel, the listing's arithmetic */
+
+/*
+ * fdk_backproject - FP32 backprojection of n_views projections.
+ * Paper Section 3.1 (Listing 1), with the zero-padded projection buffers of
+ * Section 3.3 and the image-loop blocking of Section 6.3: views are taken in
+ * batches, each batch staged into zero-padded buffers and backprojected in
+ * one pass that keeps the voxel sums in registers.
+ *   volume      device float[N^3], accumulated (+=)
+ *   N           voxels per axis, 1 <= N <= 4096
+ *   voxel_size  mm, finite and > 0
+ *   origin      host float[3], centre of voxel (0,0,0) in mm
+ *   proj_stack  device float[n_views*H*W]
+ *   n_views     >= 0 (0 is a no-op returning FDK_OK)
+ *   H, W        detector rows and columns, 1..32768
+ *   P_mats      host double[n_views*12], finite
+ *   stream      hipStream_t as void*
+ */
+int fdk_backproject(float* volume, int N, float voxel_size, const float origin[3],
+                    const float* proj_stack, int n_views, int H, int W, const double* P_mats,
+                    void* stream);
+
+/*
+ * fdk_backproject_ex - as fdk_backproject, with a choice of projection
+ * storage type and kernel.
+ *   proj_stack  device, n_views*H*W elements of proj_dtype (FDK_DTYPE_*):
+ *               FP16 and BF16 are IEEE binary16 / bfloat16 bit patterns.
+ *   view_scale  host float[n_views] or NULL: view i's pixel values are
+ *               multiplied by view_scale[i] (applied exactly when it is a
+ *               power of 4, by folding into the matrix; otherwise as an FP32
+ *               multiply).  Lets FP16 stacks be stored pre-scaled into range.
+ *   flags       FDK_KERNEL_FUSED or FDK_KERNEL_PLAIN (the plain kernel
+ *               accepts FP32 only and no view_scale).
+ * All arithmetic and the accumulation are FP32 whatever the storage type.
+ */
+int fdk_backproject_ex(float* volume, int N, float voxel_size, const float origin[3],
+                       const void* proj_stack, int proj_dtype, int n_views, int H, int W,
+                       const double* P_mats, const float* view_scale, int flags, void* stream);
+
+/*
+ * fdk_backproject_plain - the plain FP32 path: one thread per voxel, the
+ * listing's arithmetic (world coordinates, one IEEE division per
+ * coordinate, bounds-checked taps), all views of a batch accumulated in a
+ * register.  For comparison with fdk_backproject on the same GPU.
+ * Arguments as fdk_backproject.
+ */
+int fdk_backproject_plain(float* volume, int N, float voxel_size, const float origin[3],
+                          const float* proj_stack, int n_views, int H, int W,
+                          const double* P_mats, void* stream);
+
+/*
+ * fdk_forward_project - the matched cone-beam forward projector, the exact
+ * transpose of fdk_backproject: every voxel's value times 1/w^2 is spread
+ * onto the four pixels the backprojection reads, with the same bilinear
+ * weights; pixels outside the detector are dropped.  ACCUMULATES into
+ * proj_stack (+=).  Uses floating-point atomics, so results may differ
+ * between runs in the last bits.
+ *   proj_stack  device float[n_views*H*W], accumulated
+ *   volume      device float[N^3]
+ *   other arguments as fdk_backproject.
+ */
+int fdk_forward_project(float* proj_stack, int n_views, int H, int W, const double* P_mats,
+                        const float* volume, int N, float voxel_size, const float origin[3],
+                        void* stream);
+
+/*
+ * fdk_update_probe - the paper's update benchmark a[i] = s * a[i]
+ * (Section 2) over n floats of device memory, used to measure the
+ * achievable HBM bandwidth and to scale memory counters.
+ */
+int fdk_update_probe(float* a, size_t n, float s, void* stream);
+
+/*
+ * Timing of the backprojection kernels themselves.  After
+ * fdk_profile_begin(), every backprojection kernel launch is bracketed by
+ * HIP events on its stream; fdk_profile_end() waits for them and returns
+ * the summed kernel milliseconds and the launch count, then stops timing.
+ * Per thread of the caller; not for use across threads.
+ */
+int fdk_profile_begin(void);
+int fdk_profile_end(double* kernel_ms, int* launches);
+
+/* Views per backprojection launch (1..64, default 64); 0 reads it back. */
+int fdk_set_batch(int views_per_pass);
+
+/* Frees the library's staging buffers (waits for their last users). */
+int fdk_release(void);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* fdk_last_error(void);
+
+/* ABI version: (major << 16) | minor. */
+int fdk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDK_H */

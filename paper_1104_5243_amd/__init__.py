@@ -1,0 +1,231 @@
+"""MI355X (gfx950) cone-beam backprojection: Python binding of libfdk.so.
+
+Thin argument marshalling over the C ABI of include/fdk.h: every step of
+the backprojection runs in the library's HIP kernels.  PyTorch supplies the
+device memory and the stream.  There is no CPU fallback: if libfdk.so is
+missing or cannot be loaded, importing the binding's functions raises.
+
+    import paper_1104_5243_amd as fdk
+    vol = torch.zeros(N, N, N, device="cuda")
+    fdk.backproject(vol, proj, P, voxel_size, origin)   # vol += B proj
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfdk.so")
+
+FDK_OK = 0
+FDK_ERR_INVALID_ARG = -1
+FDK_ERR_HIP = -2
+FDK_ERR_UNSUPPORTED = -3
+DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
+KERNEL_FUSED, KERNEL_PLAIN = 0, 1
+
+# every symbol include/fdk.h declares
+EXPORTS = (
+    "fdk_backproject", "fdk_backproject_ex", "fdk_backproject_plain", "fdk_forward_project",
+    "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
+    "fdk_release", "fdk_last_error", "fdk_version",
+)
+
+_lib = None
+
+
+class FdkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fdk error {code}: {msg}")
+        self.code = code
+
+
+def build() -> str:
+    from . import buildlib as _b
+    global _lib
+    _lib = None
+    return _b.build()
+
+
+def lib():
+    """The loaded libfdk.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1104_5243_amd.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, fp, dp, i, f = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                            ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_float)
+        L.fdk_backproject.argtypes = [vp, i, f, fp, vp, i, i, i, dp, vp]
+        L.fdk_backproject_ex.argtypes = [vp, i, f, fp, vp, i, i, i, i, dp, fp, i, vp]
+        L.fdk_backproject_plain.argtypes = [vp, i, f, fp, vp, i, i, i, dp, vp]
+        L.fdk_forward_project.argtypes = [vp, i, i, i, dp, vp, i, f, fp, vp]
+        L.fdk_update_probe.argtypes = [vp, ctypes.c_size_t, f, vp]
+        L.fdk_profile_begin.argtypes = []
+        L.fdk_profile_end.argtypes = [dp, ctypes.POINTER(ctypes.c_int)]
+        L.fdk_set_batch.argtypes = [i]
+        L.fdk_release.argtypes = []
+        L.fdk_last_error.argtypes = []
+        L.fdk_last_error.restype = ctypes.c_char_p
+        L.fdk_version.argtypes = []
+        for name in EXPORTS:
+            if name not in ("fdk_last_error",):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise FdkError(rc, lib().fdk_last_error().decode())
+    return rc
+
+
+def last_error() -> str:
+    return lib().fdk_last_error().decode()
+
+
+def version() -> int:
+    return lib().fdk_version()
+
+
+# --------------------------------------------------------------------------
+# marshalling helpers
+# --------------------------------------------------------------------------
+def _stream_ptr(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mats(P, n_views: int):
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.float64).reshape(-1, 12))
+    if P.shape[0] != n_views:
+        raise ValueError(f"need {n_views} 3x4 matrices, got {P.shape[0]}")
+    return P, P.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _origin(origin):
+    o = np.ascontiguousarray(np.asarray(origin, dtype=np.float32).reshape(3))
+    return o, o.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _dev_tensor(t, name, dtypes, ndim=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    return t
+
+
+def _volume(volume):
+    import torch
+    _dev_tensor(volume, "volume", (torch.float32,), 3)
+    N = volume.shape[0]
+    if tuple(volume.shape) != (N, N, N):
+        raise ValueError("volume must be N x N x N, indexed [z, y, x]")
+    return N
+
+
+# --------------------------------------------------------------------------
+# entry points
+# --------------------------------------------------------------------------
+def backproject(volume, proj, P, voxel_size: float, origin, stream=None, kernel: str = "fused",
+                view_scale=None):
+    """volume[z, y, x] += sum over views of the bilinearly sampled, 1/w^2
+    weighted projections (see include/fdk.h).  proj: (n_views, H, W) device
+    tensor of float32, float16 or bfloat16; P: (n_views, 3, 4) FP64 on the
+    host; origin: world centre of voxel (0, 0, 0).  Asynchronous on `stream`
+    (default: the current stream)."""
+    import torch
+    N = _volume(volume)
+    _dev_tensor(proj, "proj", (torch.float32, torch.float16, torch.bfloat16), 3)
+    if proj.device != volume.device:
+        raise ValueError("volume and proj must be on the same device")
+    V, H, W = proj.shape
+    Pm, Pp = _mats(P, V)
+    o, op = _origin(origin)
+    dtype = {torch.float32: DTYPE_F32, torch.float16: DTYPE_F16, torch.bfloat16: DTYPE_BF16}[
+        proj.dtype]
+    flags = {"fused": KERNEL_FUSED, "plain": KERNEL_PLAIN}[kernel]
+    vs_arr, vs_ptr = None, None
+    if view_scale is not None:
+        vs_arr = np.ascontiguousarray(np.asarray(view_scale, dtype=np.float32).reshape(V))
+        vs_ptr = vs_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    with torch.cuda.device(volume.device):
+        rc = lib().fdk_backproject_ex(
+            ctypes.c_void_p(volume.data_ptr()), N, float(voxel_size), op,
+            ctypes.c_void_p(proj.data_ptr()), dtype, V, H, W, Pp, vs_ptr, flags,
+            _stream_ptr(stream, volume.device))
+    _check(rc)
+    return volume
+
+
+def backproject_plain(volume, proj, P, voxel_size: float, origin, stream=None):
+    """The plain FP32 path (one thread per voxel, the listing's arithmetic)."""
+    import torch
+    N = _volume(volume)
+    _dev_tensor(proj, "proj", (torch.float32,), 3)
+    V, H, W = proj.shape
+    Pm, Pp = _mats(P, V)
+    o, op = _origin(origin)
+    with torch.cuda.device(volume.device):
+        rc = lib().fdk_backproject_plain(
+            ctypes.c_void_p(volume.data_ptr()), N, float(voxel_size), op,
+            ctypes.c_void_p(proj.data_ptr()), V, H, W, Pp, _stream_ptr(stream, volume.device))
+    _check(rc)
+    return volume
+
+
+def forward_project(proj, volume, P, voxel_size: float, origin, stream=None):
+    """proj[i, k, j] += (B^T volume): the exact transpose of `backproject`."""
+    import torch
+    N = _volume(volume)
+    _dev_tensor(proj, "proj", (torch.float32,), 3)
+    V, H, W = proj.shape
+    Pm, Pp = _mats(P, V)
+    o, op = _origin(origin)
+    with torch.cuda.device(volume.device):
+        rc = lib().fdk_forward_project(
+            ctypes.c_void_p(proj.data_ptr()), V, H, W, Pp, ctypes.c_void_p(volume.data_ptr()), N,
+            float(voxel_size), op, _stream_ptr(stream, volume.device))
+    _check(rc)
+    return proj
+
+
+def update_probe(a, s: float = 1.0000001, stream=None):
+    """a *= s in place (the paper's update benchmark)."""
+    import torch
+    _dev_tensor(a, "a", (torch.float32,))
+    with torch.cuda.device(a.device):
+        _check(lib().fdk_update_probe(ctypes.c_void_p(a.data_ptr()), a.numel(), float(s),
+                                      _stream_ptr(stream, a.device)))
+    return a
+
+
+def profile_begin():
+    _check(lib().fdk_profile_begin())
+
+
+def profile_end():
+    """(summed backprojection-kernel milliseconds, number of launches)."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int(0)
+    _check(lib().fdk_profile_end(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def set_batch(views_per_pass: int) -> int:
+    return _check(lib().fdk_set_batch(int(views_per_pass)))
+
+
+def release():
+    _check(lib().fdk_release())

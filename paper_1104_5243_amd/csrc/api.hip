@@ -1,0 +1,426 @@
+// Host side of the C ABI declared in include/fdk.h: argument validation,
+// the FP64 matrix fold, the per-device staging buffer, kernel launches,
+// timing hooks and error reporting.
+#include "../../include/fdk.h"
+#include "fdk_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+using namespace fdk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(FDK_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- staging buffer (one per device) -------------------------------------
+struct Staging {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t last_use = nullptr;  // recorded after the last call's kernels
+};
+std::mutex g_stage_mu;
+std::unordered_map<int, Staging> g_stage;
+int g_batch = kMaxBatch;
+constexpr size_t kMaxStagingBytes = size_t(4) << 30;
+
+// ---- kernel timing (per calling thread) ----------------------------------
+struct Timing {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+};
+thread_local Timing g_timing;
+
+int timed_begin(hipStream_t s, hipEvent_t* e0)
+{
+    *e0 = nullptr;
+    if (!g_timing.on) return FDK_OK;
+    hipError_t e = hipEventCreate(e0);
+    if (e == hipSuccess) e = hipEventRecord(*e0, s);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "timing event");
+}
+
+int timed_end(hipStream_t s, hipEvent_t e0)
+{
+    if (!g_timing.on || !e0) return FDK_OK;
+    hipEvent_t e1;
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e != hipSuccess) return hip_fail(e, "timing event");
+    g_timing.ev.emplace_back(e0, e1);
+    return FDK_OK;
+}
+
+// ---- validation -----------------------------------------------------------
+int validate_common(const void* volume, int N, float voxel_size, const float* origin,
+                    const void* proj, int n_views, int H, int W, const double* P)
+{
+    if (!volume) return fail(FDK_ERR_INVALID_ARG, "volume is NULL");
+    if (N < 1 || N > 4096) return fail(FDK_ERR_INVALID_ARG, "N=%d outside [1, 4096]", N);
+    if (!(std::isfinite(voxel_size) && voxel_size > 0.0f))
+        return fail(FDK_ERR_INVALID_ARG, "voxel_size must be finite and > 0");
+    if (!origin) return fail(FDK_ERR_INVALID_ARG, "origin is NULL");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(origin[c])) return fail(FDK_ERR_INVALID_ARG, "origin not finite");
+    if (n_views < 0) return fail(FDK_ERR_INVALID_ARG, "n_views=%d < 0", n_views);
+    if (H < 1 || H > 32768 || W < 1 || W > 32768)
+        return fail(FDK_ERR_INVALID_ARG, "detector %dx%d outside [1, 32768]^2", W, H);
+    if (n_views == 0) return FDK_OK;
+    if (!proj) return fail(FDK_ERR_INVALID_ARG, "proj_stack is NULL");
+    if (!P) return fail(FDK_ERR_INVALID_ARG, "P_mats is NULL");
+    for (long long i = 0; i < 12LL * n_views; ++i)
+        if (!std::isfinite(P[i])) return fail(FDK_ERR_INVALID_ARG, "P_mats[%lld] not finite", i);
+    return FDK_OK;
+}
+
+// ---- geometry fold (FP64, rounded once to FP32) ---------------------------
+// Centred index frame: voxel index x = x' + c with c = (N-1)/2, world
+// X = origin + voxel_size * x.  The integer principal point (ku, kv) is
+// subtracted from the u and v rows so that u' = u - ku stays small, and
+// the view's scale s folds in as 1/sqrt(s) (exact for powers of 4).
+void fold_matrix(const double* P, int N, double vs, const float* origin, int ku, int kv,
+                 double lambda, double Q[12])
+{
+    const double c = 0.5 * (N - 1);
+    for (int r = 0; r < 3; ++r) {
+        double t = P[4 * r + 3];
+        for (int k = 0; k < 3; ++k) {
+            Q[4 * r + k] = vs * P[4 * r + k] * lambda;
+            t += P[4 * r + k] * ((double)origin[k] + vs * c);
+        }
+        Q[4 * r + 3] = t * lambda;
+    }
+    for (int k = 0; k < 4; ++k) {
+        Q[k] -= ku * Q[8 + k];
+        Q[4 + k] -= kv * Q[8 + k];
+    }
+}
+
+// True if some voxel of the centred box [-c, c]^3 may have w <= 0 (or so
+// close to 0 that its FP32 value could be) for this folded matrix.
+bool needs_wcheck(const double Q[12], double c)
+{
+    double wmin = INFINITY, wmax = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+        double x = (corner & 1) ? c : -c, y = (corner & 2) ? c : -c, z = (corner & 4) ? c : -c;
+        double w = Q[8] * x + Q[9] * y + Q[10] * z + Q[11];
+        wmin = std::fmin(wmin, w);
+        wmax = std::fmax(wmax, std::fabs(w));
+    }
+    return !(wmin > 1e-4 * wmax);
+}
+
+int storage_size(int dtype)
+{
+    return dtype == FDK_DTYPE_F32 ? 4 : 2;
+}
+
+// Acquire the calling device's staging buffer with at least `bytes`, and
+// order `stream` after the previous call that used it.  Caller holds the
+// staging mutex.
+int acquire_staging(size_t bytes, hipStream_t stream, Staging** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Staging& st = g_stage[dev];
+    if (!st.last_use) {
+        e = hipEventCreateWithFlags(&st.last_use, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        e = hipEventRecord(st.last_use, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    if (st.bytes < bytes) {
+        e = hipEventSynchronize(st.last_use);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        if (st.ptr) {
+            e = hipFree(st.ptr);
+            st.ptr = nullptr;
+            st.bytes = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipFree(staging)");
+        }
+        e = hipMalloc(&st.ptr, bytes);
+        if (e != hipSuccess) {
+            st.ptr = nullptr;
+            return hip_fail(e, "hipMalloc(staging)");
+        }
+        st.bytes = bytes;
+    }
+    e = hipStreamWaitEvent(stream, st.last_use, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    *out = &st;
+    return FDK_OK;
+}
+
+int run_fused(float* volume, int N, float voxel_size, const float* origin, const void* proj,
+              int dtype, int n_views, int H, int W, const double* P, const float* view_scale,
+              hipStream_t stream)
+{
+    const int ku = (W - 1) / 2, kv = (H - 1) / 2;
+    const int Hp = H + 2 * kPad;
+    const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
+    const size_t esz = storage_size(dtype);
+    const size_t plane_bytes = (size_t)Hp * Wp * esz;
+    if (plane_bytes >= (size_t(1) << 31))
+        return fail(FDK_ERR_UNSUPPORTED, "staged view of %zu bytes exceeds 2 GiB", plane_bytes);
+    int batch = g_batch;
+    if ((size_t)batch * plane_bytes > kMaxStagingBytes)
+        batch = (int)std::max<size_t>(1, kMaxStagingBytes / plane_bytes);
+    batch = std::min(batch, n_views);
+
+    FusedArgs A = {};
+    A.vol = volume;
+    A.plane = (long long)Hp * Wp;
+    A.N = N;
+    A.nz = N;
+    A.z_first = 0;
+    A.Wp = Wp;
+    A.lo_u = (float)(-ku - kPad);
+    A.hi_u = (float)(W - ku) + 0.5f;
+    A.lo_v = (float)(-kv - kPad);
+    A.hi_v = (float)(H - kv) + 0.5f;
+    A.origin_off = (kv + kPad) * Wp + (ku + kPad);
+    A.c = 0.5f * (float)(N - 1);
+    A.tiles_x = (N + kFusedTile - 1) / kFusedTile;
+    A.tiles_y = A.tiles_x;
+    A.zchunks = (N + kFusedZ - 1) / kFusedZ;
+    const long long blocks = (long long)A.tiles_x * A.tiles_y * A.zchunks;
+    A.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    Staging* st = nullptr;
+    int rc = acquire_staging((size_t)batch * plane_bytes, stream, &st);
+    if (rc != FDK_OK) return rc;
+    A.img = st->ptr;
+
+    const double c = 0.5 * (N - 1);
+    for (int v0 = 0; v0 < n_views; v0 += batch) {
+        const int cnt = std::min(batch, n_views - v0);
+        StageArgs S;
+        S.src = (const char*)proj + (size_t)v0 * H * W * esz;
+        S.dst = st->ptr;
+        S.H = H;
+        S.W = W;
+        S.Hp = Hp;
+        S.Wp = Wp;
+        S.count = cnt;
+        hipError_t e = launch_stage(S, dtype, stream);
+        if (e != hipSuccess) return hip_fail(e, "stage launch");
+
+        bool wcheck = false;
+        A.count = cnt;
+        for (int j = 0; j < cnt; ++j) {
+            double lambda = 1.0;
+            if (view_scale) lambda = 1.0 / std::sqrt((double)view_scale[v0 + j]);
+            double Q[12];
+            fold_matrix(P + 12 * (size_t)(v0 + j), N, voxel_size, origin, ku, kv, lambda, Q);
+            wcheck |= needs_wcheck(Q, c);
+            for (int k = 0; k < 12; ++k) A.m[j][k] = (float)Q[k];
+        }
+        hipEvent_t t0;
+        if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
+        e = launch_fused(A, dtype, wcheck, stream);
+        if (e != hipSuccess) return hip_fail(e, "backprojection launch");
+        if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
+    }
+    hipError_t e = hipEventRecord(st->last_use, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return FDK_OK;
+}
+
+int run_plain(float* volume, int N, float voxel_size, const float* origin, const float* proj,
+              int n_views, int H, int W, const double* P, hipStream_t stream)
+{
+    PlainArgs A = {};
+    A.vol = volume;
+    A.N = N;
+    A.H = H;
+    A.W = W;
+    A.ox = origin[0];
+    A.oy = origin[1];
+    A.oz = origin[2];
+    A.vs = voxel_size;
+    const int batch = std::min(g_batch, n_views);
+    for (int v0 = 0; v0 < n_views; v0 += batch) {
+        const int cnt = std::min(batch, n_views - v0);
+        A.proj = proj + (size_t)v0 * H * W;
+        A.count = cnt;
+        for (int j = 0; j < cnt; ++j)
+            for (int k = 0; k < 12; ++k) A.m[j][k] = (float)P[12 * (size_t)(v0 + j) + k];
+        hipEvent_t t0;
+        int rc;
+        if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
+        hipError_t e = launch_plain(A, stream);
+        if (e != hipSuccess) return hip_fail(e, "plain backprojection launch");
+        if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
+    }
+    return FDK_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int fdk_backproject_ex(float* volume, int N, float voxel_size, const float origin[3],
+                       const void* proj_stack, int proj_dtype, int n_views, int H, int W,
+                       const double* P_mats, const float* view_scale, int flags, void* stream)
+{
+    g_err.clear();
+    int rc = validate_common(volume, N, voxel_size, origin, proj_stack, n_views, H, W, P_mats);
+    if (rc != FDK_OK || n_views == 0) return rc;
+    if (proj_dtype != FDK_DTYPE_F32 && proj_dtype != FDK_DTYPE_F16 && proj_dtype != FDK_DTYPE_BF16)
+        return fail(FDK_ERR_INVALID_ARG, "unknown proj_dtype %d", proj_dtype);
+    if (view_scale)
+        for (int i = 0; i < n_views; ++i)
+            if (!(std::isfinite(view_scale[i]) && view_scale[i] > 0.0f))
+                return fail(FDK_ERR_INVALID_ARG, "view_scale[%d] must be finite and > 0", i);
+    hipStream_t s = (hipStream_t)stream;
+    if (flags == FDK_KERNEL_PLAIN) {
+        if (proj_dtype != FDK_DTYPE_F32 || view_scale)
+            return fail(FDK_ERR_UNSUPPORTED, "the plain kernel takes FP32 and no view_scale");
+        return run_plain(volume, N, voxel_size, origin, (const float*)proj_stack, n_views, H, W,
+                         P_mats, s);
+    }
+    if (flags != FDK_KERNEL_FUSED) return fail(FDK_ERR_INVALID_ARG, "unknown flags %d", flags);
+    return run_fused(volume, N, voxel_size, origin, proj_stack, proj_dtype, n_views, H, W, P_mats,
+                     view_scale, s);
+}
+
+int fdk_backproject(float* volume, int N, float voxel_size, const float origin[3],
+                    const float* proj_stack, int n_views, int H, int W, const double* P_mats,
+                    void* stream)
+{
+    return fdk_backproject_ex(volume, N, voxel_size, origin, proj_stack, FDK_DTYPE_F32, n_views,
+                              H, W, P_mats, nullptr, FDK_KERNEL_FUSED, stream);
+}
+
+int fdk_backproject_plain(float* volume, int N, float voxel_size, const float origin[3],
+                          const float* proj_stack, int n_views, int H, int W,
+                          const double* P_mats, void* stream)
+{
+    return fdk_backproject_ex(volume, N, voxel_size, origin, proj_stack, FDK_DTYPE_F32, n_views,
+                              H, W, P_mats, nullptr, FDK_KERNEL_PLAIN, stream);
+}
+
+int fdk_forward_project(float* proj_stack, int n_views, int H, int W, const double* P_mats,
+                        const float* volume, int N, float voxel_size, const float origin[3],
+                        void* stream)
+{
+    g_err.clear();
+    (void)proj_stack; (void)n_views; (void)H; (void)W; (void)P_mats; (void)volume; (void)N;
+    (void)voxel_size; (void)origin; (void)stream;
+    return fail(FDK_ERR_UNSUPPORTED, "fdk_forward_project is not built yet");
+}
+
+int fdk_update_probe(float* a, size_t n, float s, void* stream)
+{
+    g_err.clear();
+    if (!a && n) return fail(FDK_ERR_INVALID_ARG, "a is NULL");
+    if (n == 0) return FDK_OK;
+    hipError_t e = launch_update_probe(a, n, s, (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "update probe launch");
+}
+
+int fdk_profile_begin(void)
+{
+    g_err.clear();
+    for (auto& p : g_timing.ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    g_timing.ev.clear();
+    g_timing.on = true;
+    return FDK_OK;
+}
+
+int fdk_profile_end(double* kernel_ms, int* launches)
+{
+    g_err.clear();
+    double total = 0.0;
+    int rc = FDK_OK;
+    for (auto& p : g_timing.ev) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+        if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "timing readback");
+        total += ms;
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (kernel_ms) *kernel_ms = total;
+    if (launches) *launches = (int)g_timing.ev.size();
+    g_timing.ev.clear();
+    g_timing.on = false;
+    return rc;
+}
+
+int fdk_set_batch(int views_per_pass)
+{
+    g_err.clear();
+    if (views_per_pass == 0) return g_batch;
+    if (views_per_pass < 1 || views_per_pass > kMaxBatch)
+        return fail(FDK_ERR_INVALID_ARG, "views_per_pass=%d outside [1, %d]", views_per_pass,
+                    kMaxBatch);
+    g_batch = views_per_pass;
+    return g_batch;
+}
+
+int fdk_release(void)
+{
+    g_err.clear();
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    int rc = FDK_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_stage) {
+        Staging& st = kv.second;
+        (void)hipSetDevice(kv.first);
+        if (st.last_use) {
+            hipError_t e = hipEventSynchronize(st.last_use);
+            if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "hipEventSynchronize");
+            (void)hipEventDestroy(st.last_use);
+        }
+        if (st.ptr) {
+            hipError_t e = hipFree(st.ptr);
+            if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "hipFree(staging)");
+        }
+    }
+    g_stage.clear();
+    (void)hipSetDevice(cur);
+    return rc;
+}
+
+const char* fdk_last_error(void)
+{
+    return g_err.c_str();
+}
+
+int fdk_version(void)
+{
+    return (1 << 16) | 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Internal declarations shared by the host entry points and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdk {
+
+// Views per backprojection launch; their matrices travel in the kernel
+// arguments (12 floats each), which keeps every call free of host-to-device
+// copies and under the 4 KiB kernel-argument limit.
+constexpr int kMaxBatch = 64;
+
+// Zero border of a staged projection plane (pixels on every side).  Taps
+// are clamped into [-2, W] x [-2, H], so a 2-pixel border is enough for
+// every clamped tap pair to read zeros outside the detector.
+constexpr int kPad = 2;
+
+enum StorageType { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+// Arguments of the fused kernel.  Matrices are in the centred index frame:
+// for voxel (x, y, z) with x' = x - c (likewise y', z'), (u'w, v'w, w) =
+// m * (x', y', z', 1), and the pixel coordinate is u = u' + ku.
+struct FusedArgs {
+    float* vol;          // N^3 (or a z-slab of it; see z_first, nz)
+    const void* img;     // staged planes of this batch, plane elements apart
+    long long plane;     // elements per staged plane
+    int N;               // x and y extent; also the z stride base
+    int nz;              // number of z slices written (z_first .. z_first+nz-1)
+    int z_first;         // first z slice
+    int Wp;              // staged row pitch (elements)
+    float lo_u, hi_u;    // clamp range of u' before the floor
+    float lo_v, hi_v;
+    int origin_off;      // element offset of pixel (ku, kv) inside a plane
+    float c;             // (N-1)/2
+    int count;           // views in this batch
+    int tiles_x, tiles_y, zchunks;
+    int xcd_remap;       // 1: spread consecutive tiles over XCD-local ranges
+    float m[kMaxBatch][12];
+};
+
+// Arguments of the plain kernel: world-coordinate matrices (FP32 roundings
+// of the caller's), unpadded projections.
+struct PlainArgs {
+    float* vol;
+    const float* proj;   // first view of the batch, H*W floats per view
+    int N, H, W;
+    float ox, oy, oz, vs;
+    int count;
+    float m[kMaxBatch][12];
+};
+
+struct StageArgs {
+    const void* src;     // first view of the batch, H*W elements per view
+    void* dst;           // count planes of Hp*Wp elements
+    int H, W, Hp, Wp;
+    int count;
+};
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s);
+hipError_t launch_fused(const FusedArgs& a, int storage, bool wcheck, hipStream_t s);
+hipError_t launch_plain(const PlainArgs& a, hipStream_t s);
+hipError_t launch_update_probe(float* a, size_t n, float s, hipStream_t st);
+
+constexpr int kFusedZ = 16;      // z voxels per thread in the fused kernel
+constexpr int kFusedTile = 16;   // x and y columns per 256-thread workgroup
+
+}  // namespace fdk

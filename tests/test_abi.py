@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every symbol include/fdk.h declares, and
+rejects invalid arguments before touching the GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1104_5243_amd as fdk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdk.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdk_\w+)\s*\(", text)))
+
+
+def test_header_declares_what_the_binding_lists():
+    assert declared_symbols() == sorted(fdk.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = fdk.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_version():
+    assert fdk.version() >> 16 == 1
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def _call(**over):
+    P = np.tile(np.eye(3, 4), (2, 1, 1)).astype(np.float64)
+    o = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    args = dict(volume=FAKE, N=8, vs=1.0, origin=o, proj=FAKE, dtype=0, n_views=2, H=4, W=4,
+                P=P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), scale=None, flags=0)
+    args.update(over)
+    rc = fdk.lib().fdk_backproject_ex(args["volume"], args["N"], args["vs"], args["origin"],
+                                      args["proj"], args["dtype"], args["n_views"], args["H"],
+                                      args["W"], args["P"], args["scale"], args["flags"], None)
+    return rc, fdk.last_error()
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(volume=None), "volume"),
+    (dict(N=0), "N=0"),
+    (dict(N=5000), "N=5000"),
+    (dict(vs=0.0), "voxel_size"),
+    (dict(vs=float("nan")), "voxel_size"),
+    (dict(origin=None), "origin"),
+    (dict(n_views=-1), "n_views"),
+    (dict(H=0), "detector"),
+    (dict(W=40000), "detector"),
+    (dict(proj=None), "proj_stack"),
+    (dict(P=None), "P_mats"),
+    (dict(dtype=7), "proj_dtype"),
+    (dict(flags=9), "flags"),
+])
+def test_invalid_arguments_are_rejected(over, needle):
+    rc, msg = _call(**over)
+    assert rc == fdk.FDK_ERR_INVALID_ARG
+    assert needle in msg
+
+
+def test_nonfinite_matrix_rejected():
+    P = np.tile(np.eye(3, 4), (2, 1, 1)).astype(np.float64)
+    P[1, 2, 3] = np.inf
+    rc, msg = _call(P=P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert rc == fdk.FDK_ERR_INVALID_ARG and "P_mats[23]" in msg
+
+
+def test_bad_view_scale_rejected():
+    s = (ctypes.c_float * 2)(1.0, -4.0)
+    rc, msg = _call(scale=s)
+    assert rc == fdk.FDK_ERR_INVALID_ARG and "view_scale[1]" in msg
+
+
+def test_plain_kernel_rejects_reduced_precision():
+    rc, msg = _call(dtype=1, flags=1)
+    assert rc == fdk.FDK_ERR_UNSUPPORTED
+
+
+def test_zero_views_is_a_noop_without_pointers():
+    rc, _ = _call(n_views=0, proj=None, P=None)
+    assert rc == fdk.FDK_OK
+
+
+def test_batch_setting():
+    L = fdk.lib()
+    old = L.fdk_set_batch(0)
+    assert 1 <= old <= 64
+    assert L.fdk_set_batch(65) == fdk.FDK_ERR_INVALID_ARG
+    assert L.fdk_set_batch(7) == 7
+    assert L.fdk_set_batch(old) == old
