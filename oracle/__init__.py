@@ -51,6 +51,7 @@ def _load():
         lib.oracle_backproject_points.argtypes = [dp, ip, ctypes.c_longlong, i,
                                                   ctypes.c_double, dp, fp, i, i, i, dp]
         lib.oracle_forward_project.argtypes = [dp, i, i, i, dp, dp, i, ctypes.c_double, dp]
+        lib.oracle_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -122,6 +123,11 @@ def forward_project(vol, P, H: int, W: int, voxel_size: float, origin) -> np.nda
     if rc != 0:
         raise ValueError("oracle_forward_project: invalid arguments")
     return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops run on."""
+    return int(_load().oracle_threads())
 
 
 # --------------------------------------------------------------------------

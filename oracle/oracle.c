@@ -39,6 +39,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <omp.h>
 
 /* Zero-extended pixel read T(j, k). */
 static inline double tap(const float* I, int H, int W, long long j, long long k)
@@ -186,4 +187,16 @@ int oracle_forward_project(double* F, int n_views, int H, int W, const double* P
         }
     }
     return 0;
+}
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
 }

@@ -211,6 +211,30 @@ def update_probe(a, s: float = 1.0000001, stream=None):
     return a
 
 
+def to_storage(proj, dtype):
+    """Convert an FP32 (n_views, H, W) device stack to reduced-precision
+    storage for `backproject`.  Returns (stack, view_scale): for float16 each
+    view is multiplied by a power of 4 that brings its largest magnitude to
+    [2^12, 2^14) before rounding (filtered projections are ~1e-4, where FP16
+    is subnormal), and view_scale = 4^-k undoes it exactly inside the
+    library.  For bfloat16 (FP32's range) view_scale is None."""
+    import torch
+    if dtype == torch.float32:
+        return proj, None
+    if dtype == torch.bfloat16:
+        return proj.to(torch.bfloat16), None
+    if dtype != torch.float16:
+        raise ValueError(f"unsupported storage dtype {dtype}")
+    amax = proj.abs().amax(dim=(1, 2)).double().cpu().numpy()
+    k = np.zeros(len(amax))
+    nz = amax > 0
+    k[nz] = np.floor(np.log(2.0 ** 14 / amax[nz]) / np.log(4.0))
+    k = np.clip(k, -60, 60)
+    up = torch.from_numpy(4.0 ** k).to(device=proj.device, dtype=torch.float32)
+    stack = (proj * up[:, None, None]).to(torch.float16)
+    return stack, (4.0 ** -k).astype(np.float32)
+
+
 def profile_begin():
     _check(lib().fdk_profile_begin())
 

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -44,6 +46,18 @@ struct Staging {
 std::mutex g_stage_mu;
 std::unordered_map<int, Staging> g_stage;
 int g_batch = kMaxBatch;
+
+// Staged layout of the fused path (tuning knob; FDK_LAYOUT=rows|pairs|quads
+// in the environment overrides the default at load time).
+int initial_layout()
+{
+    const char* e = std::getenv("FDK_LAYOUT");
+    if (e && !std::strcmp(e, "rows")) return kRows;
+    if (e && !std::strcmp(e, "pairs")) return kPairs;
+    if (e && !std::strcmp(e, "quads")) return kQuads;
+    return kPairs;
+}
+int g_layout = initial_layout();
 constexpr size_t kMaxStagingBytes = size_t(4) << 30;
 
 // ---- kernel timing (per calling thread) ----------------------------------
@@ -132,6 +146,31 @@ bool needs_wcheck(const double Q[12], double c)
     return !(wmin > 1e-4 * wmax);
 }
 
+// Unit direction from the volume centre (index frame) towards the source:
+// the source is the null vector of the 3x4 matrix, the intersection of the
+// planes of its three rows.
+void source_direction(const double Q[12], double d[3])
+{
+    const double* a = Q;
+    const double* b = Q + 4;
+    const double* c = Q + 8;
+    // homogeneous null vector by cofactors: s_k = (-1)^k det(Q without column k)
+    auto det3 = [](double a0, double a1, double a2, double b0, double b1, double b2, double c0,
+                   double c1, double c2) {
+        return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
+    };
+    const double s0 = det3(a[1], a[2], a[3], b[1], b[2], b[3], c[1], c[2], c[3]);
+    const double s1 = -det3(a[0], a[2], a[3], b[0], b[2], b[3], c[0], c[2], c[3]);
+    const double s2 = det3(a[0], a[1], a[3], b[0], b[1], b[3], c[0], c[1], c[3]);
+    const double s3 = -det3(a[0], a[1], a[2], b[0], b[1], b[2], c[0], c[1], c[2]);
+    // finite source: direction s/s3 from the centre (the origin of the frame)
+    double v[3] = {s0, s1, s2};
+    if (s3 != 0.0)
+        for (int k = 0; k < 3; ++k) v[k] /= s3;
+    const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int k = 0; k < 3; ++k) d[k] = n > 0.0 ? v[k] / n : 0.0;
+}
+
 int storage_size(int dtype)
 {
     return dtype == FDK_DTYPE_F32 ? 4 : 2;
@@ -182,7 +221,9 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     const int Hp = H + 2 * kPad;
     const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
     const size_t esz = storage_size(dtype);
-    const size_t plane_bytes = (size_t)Hp * Wp * esz;
+    const int layout = g_layout;
+    const size_t elem = esz * (layout == kRows ? 1 : layout == kPairs ? 2 : 4);
+    const size_t plane_bytes = (size_t)Hp * Wp * elem;
     if (plane_bytes >= (size_t(1) << 31))
         return fail(FDK_ERR_UNSUPPORTED, "staged view of %zu bytes exceeds 2 GiB", plane_bytes);
     int batch = g_batch;
@@ -201,10 +242,18 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     A.hi_u = (float)(W - ku) + 0.5f;
     A.lo_v = (float)(-kv - kPad);
     A.hi_v = (float)(H - kv) + 0.5f;
+    // u = u' + ku.  Zero contribution iff u <= -1 or u >= W (likewise v);
+    // floor(u) stays in [-2, W] iff u in [-2, W + 1).  Margins of 0.5 pixel.
+    A.skip_lo_u = (float)(-1 - ku) - 0.5f;
+    A.skip_hi_u = (float)(W - ku) + 0.5f;
+    A.skip_lo_v = (float)(-1 - kv) - 0.5f;
+    A.skip_hi_v = (float)(H - kv) + 0.5f;
+    A.in_lo_u = (float)(-1 - ku) - 0.5f;
+    A.in_lo_v = (float)(-1 - kv) - 0.5f;
     A.origin_off = (kv + kPad) * Wp + (ku + kPad);
     A.c = 0.5f * (float)(N - 1);
-    A.tiles_x = (N + kFusedTile - 1) / kFusedTile;
-    A.tiles_y = A.tiles_x;
+    A.tiles_x = (N + kTileX - 1) / kTileX;
+    A.tiles_y = (N + kTileY - 1) / kTileY;
     A.zchunks = (N + kFusedZ - 1) / kFusedZ;
     const long long blocks = (long long)A.tiles_x * A.tiles_y * A.zchunks;
     A.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
@@ -226,11 +275,13 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
         S.Hp = Hp;
         S.Wp = Wp;
         S.count = cnt;
+        S.layout = layout;
         hipError_t e = launch_stage(S, dtype, stream);
         if (e != hipSuccess) return hip_fail(e, "stage launch");
 
         bool wcheck = false;
         A.count = cnt;
+        double ray[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j < cnt; ++j) {
             double lambda = 1.0;
             if (view_scale) lambda = 1.0 / std::sqrt((double)view_scale[v0 + j]);
@@ -238,10 +289,14 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
             fold_matrix(P + 12 * (size_t)(v0 + j), N, voxel_size, origin, ku, kv, lambda, Q);
             wcheck |= needs_wcheck(Q, c);
             for (int k = 0; k < 12; ++k) A.m[j][k] = (float)Q[k];
+            double d[3];
+            source_direction(Q, d);
+            for (int k = 0; k < 3; ++k) ray[k] += std::fabs(d[k]);
         }
+        A.y_fastest = ray[1] > ray[0] ? 1 : 0;
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
-        e = launch_fused(A, dtype, wcheck, stream);
+        e = launch_fused(A, dtype, layout, wcheck, stream);
         if (e != hipSuccess) return hip_fail(e, "backprojection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
     }

@@ -30,30 +30,6 @@ struct TF32 { using elem = float; };
 struct TF16 { using elem = uint16_t; };
 struct TBF16 { using elem = uint16_t; };
 
-__device__ __forceinline__ void load_pair(TF32, const float* p, float& a, float& b)
-{
-    float2 t;
-    __builtin_memcpy(&t, p, sizeof(t));  // 4-byte aligned 8-byte load
-    a = t.x;
-    b = t.y;
-}
-
-__device__ __forceinline__ void load_pair(TF16, const uint16_t* p, float& a, float& b)
-{
-    uint32_t t;
-    __builtin_memcpy(&t, p, sizeof(t));
-    a = (float)__builtin_bit_cast(_Float16, (uint16_t)(t & 0xffffu));
-    b = (float)__builtin_bit_cast(_Float16, (uint16_t)(t >> 16));
-}
-
-__device__ __forceinline__ void load_pair(TBF16, const uint16_t* p, float& a, float& b)
-{
-    uint32_t t;
-    __builtin_memcpy(&t, p, sizeof(t));
-    a = __builtin_bit_cast(float, t << 16);
-    b = __builtin_bit_cast(float, t & 0xffff0000u);
-}
-
 // floor(x) as an integer in one instruction (x is finite and clamped).
 __device__ __forceinline__ int cvt_floor(float x)
 {
@@ -74,26 +50,51 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
 // stage
 // ---------------------------------------------------------------------------
 template <typename E>
+__device__ __forceinline__ E staged_pixel(const StageArgs& a, const E* src, int row, int col)
+{
+    const int j = col - kPad, k = row - kPad;
+    return (j >= 0 && j < a.W && k >= 0 && k < a.H) ? src[(size_t)k * a.W + j] : E(0);
+}
+
+template <typename E, int LAYOUT>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs a)
 {
     const int col = blockIdx.x * 256 + threadIdx.x;
     const int row = blockIdx.y;
     const int view = blockIdx.z;
     if (col >= a.Wp) return;
-    const int j = col - kPad, k = row - kPad;
     const E* src = (const E*)a.src + (size_t)view * a.H * a.W;
-    E v = E(0);
-    if (j >= 0 && j < a.W && k >= 0 && k < a.H) v = src[(size_t)k * a.W + j];
-    ((E*)a.dst)[((size_t)view * a.Hp + row) * a.Wp + col] = v;
+    const size_t e = ((size_t)view * a.Hp + row) * a.Wp + col;
+    E* dst = (E*)a.dst;
+    if (LAYOUT == kRows) {
+        dst[e] = staged_pixel(a, src, row, col);
+    } else if (LAYOUT == kPairs) {
+        E v[2] = {staged_pixel(a, src, row, col), staged_pixel(a, src, row + 1, col)};
+        __builtin_memcpy(dst + 2 * e, v, sizeof(v));
+    } else {
+        E v[4] = {staged_pixel(a, src, row, col), staged_pixel(a, src, row, col + 1),
+                  staged_pixel(a, src, row + 1, col), staged_pixel(a, src, row + 1, col + 1)};
+        __builtin_memcpy(dst + 4 * e, v, sizeof(v));
+    }
 }
 
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s)
 {
     dim3 grid((a.Wp + 255) / 256, a.Hp, a.count);
+#define FDK_STAGE(E)                                                                     \
+    do {                                                                                 \
+        if (a.layout == kRows)                                                           \
+            hipLaunchKernelGGL((stage_kernel<E, kRows>), grid, dim3(256), 0, s, a);      \
+        else if (a.layout == kPairs)                                                     \
+            hipLaunchKernelGGL((stage_kernel<E, kPairs>), grid, dim3(256), 0, s, a);     \
+        else                                                                             \
+            hipLaunchKernelGGL((stage_kernel<E, kQuads>), grid, dim3(256), 0, s, a);     \
+    } while (0)
     if (storage == kF32)
-        hipLaunchKernelGGL(stage_kernel<float>, grid, dim3(256), 0, s, a);
+        FDK_STAGE(float);
     else
-        hipLaunchKernelGGL(stage_kernel<uint16_t>, grid, dim3(256), 0, s, a);
+        FDK_STAGE(uint16_t);
+#undef FDK_STAGE
     return hipGetLastError();
 }
 
@@ -110,104 +111,231 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
                                              0x00020000);
 }
 
-__device__ __forceinline__ void load_pair_buf(TF32, __amdgpu_buffer_rsrc_t r, uint32_t off,
-                                              uint32_t soff, float& a, float& b)
+// The four taps (tl, tr, bl, br) of element (iv, iu): `off` is the byte
+// offset of that element, `row` the byte stride of a plane row.  (The
+// buffer-load builtins' vector results are reinterpreted whole; extracting
+// their elements one by one is miscompiled by this compiler into a single
+// dword load.)
+template <int LAYOUT>
+__device__ __forceinline__ void load_taps(TF32, __amdgpu_buffer_rsrc_t r, uint32_t off,
+                                          uint32_t row, float& tl, float& tr, float& bl,
+                                          float& br)
 {
-    auto t = __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0);
-    float2 f = __builtin_bit_cast(float2, t);
-    a = f.x;
-    b = f.y;
+    if (LAYOUT == kRows) {
+        const float2 t = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        const float2 b = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, row, 0));
+        tl = t.x; tr = t.y; bl = b.x; br = b.y;
+    } else if (LAYOUT == kPairs) {  // (tl, bl, tr, br)
+        const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        tl = q.x; bl = q.y; tr = q.z; br = q.w;
+    } else {  // (tl, tr, bl, br)
+        const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        tl = q.x; tr = q.y; bl = q.z; br = q.w;
+    }
 }
 
-__device__ __forceinline__ void load_pair_buf(TF16, __amdgpu_buffer_rsrc_t r, uint32_t off,
-                                              uint32_t soff, float& a, float& b)
+// 16-bit storage: the two dwords holding the four taps, as loaded.
+//   rows : w0 = (tl, tr), w1 = (bl, br)   [low half first]
+//   pairs: w0 = (tl, bl), w1 = (tr, br)
+//   quads: w0 = (tl, tr), w1 = (bl, br)
+template <int LAYOUT>
+__device__ __forceinline__ uint2 load_taps16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t row)
 {
-    uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0);
-    a = (float)__builtin_bit_cast(_Float16, (uint16_t)(t & 0xffffu));
-    b = (float)__builtin_bit_cast(_Float16, (uint16_t)(t >> 16));
+    if (LAYOUT == kRows) {
+        uint2 q;
+        q.x = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        q.y = __builtin_amdgcn_raw_buffer_load_b32(r, off, row, 0);
+        return q;
+    }
+    return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
-__device__ __forceinline__ void load_pair_buf(TBF16, __amdgpu_buffer_rsrc_t r, uint32_t off,
-                                              uint32_t soff, float& a, float& b)
+__device__ __forceinline__ float h_lo(uint32_t w)
 {
-    uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0);
-    a = __builtin_bit_cast(float, t << 16);
-    b = __builtin_bit_cast(float, t & 0xffff0000u);
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+__device__ __forceinline__ float h_hi(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+__device__ __forceinline__ float b_lo(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__device__ __forceinline__ float b_hi(uint32_t w)
+{
+    return __builtin_bit_cast(float, w & 0xffff0000u);
+}
+
+// bilinear value from FP16 taps: each row is left + au * (right - left)
+// evaluated as fma(au, right, fma(-au, left, left)), so that the FP16
+// operands feed mixed-precision FMAs directly (no conversions).
+__device__ __forceinline__ float lerp16(float a, float left, float right)
+{
+    return fmaf(a, right, fmaf(-a, left, left));
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ float bilerp16(TF16, uint2 q, float au, float av)
+{
+    float top, bot;
+    if (LAYOUT == kPairs) {
+        top = lerp16(au, h_lo(q.x), h_lo(q.y));
+        bot = lerp16(au, h_hi(q.x), h_hi(q.y));
+    } else {
+        top = lerp16(au, h_lo(q.x), h_hi(q.x));
+        bot = lerp16(au, h_lo(q.y), h_hi(q.y));
+    }
+    return fmaf(av, bot - top, top);
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ float bilerp16(TBF16, uint2 q, float au, float av)
+{
+    float tl, tr, bl, br;
+    if (LAYOUT == kPairs) {
+        tl = b_lo(q.x); bl = b_hi(q.x); tr = b_lo(q.y); br = b_hi(q.y);
+    } else {
+        tl = b_lo(q.x); tr = b_hi(q.x); bl = b_lo(q.y); br = b_hi(q.y);
+    }
+    const float top = fmaf(au, tr - tl, tl);
+    const float bot = fmaf(au, br - bl, bl);
+    return fmaf(av, bot - top, top);
 }
 
 // z voxels whose loads are issued together before their interpolation.
-constexpr int kGroup = 4;
+#ifndef FDK_GROUP
+#define FDK_GROUP 4
+#endif
+constexpr int kGroup = FDK_GROUP;
+static_assert(kWaveX * kWaveY == 64, "a wave covers 64 columns");
 
-template <typename TT, bool WCHECK>
-__global__ __launch_bounds__(256) void bp_fused_kernel(const FusedArgs A)
+// One view's contribution to the kFusedZ voxels of this thread.  CLAMP
+// selects the clamped tap addressing (needed when some voxel of the wave
+// may project outside the zero border of the staged plane).
+template <typename TT, int LAYOUT, bool WCHECK, bool CLAMP>
+__device__ __forceinline__ void accumulate_view(const FusedArgs& A, const float* m, float xp,
+                                                float yp, float zp0,
+                                                __amdgpu_buffer_rsrc_t rsrc,
+                                                float (&acc)[kFusedZ])
 {
     using E = typename TT::elem;
+    constexpr bool kIsF32 = sizeof(E) == 4;
+    constexpr uint32_t kElem = sizeof(E) * (LAYOUT == kRows ? 1 : LAYOUT == kPairs ? 2 : 4);
+    const int Wp = A.Wp;
+    const uint32_t row_bytes = (uint32_t)Wp * kElem;
+    const uint32_t centre_bytes = (uint32_t)A.origin_off * kElem;
+    const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
+    const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
+    const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
+#pragma unroll
+    for (int g = 0; g < kFusedZ; g += kGroup) {
+        float au[kGroup], av[kGroup], r2[kGroup];
+        float tl[kGroup], tr[kGroup], bl[kGroup], br[kGroup];  // FP32 storage
+        uint2 raw[kGroup];                                      // 16-bit storage
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            const float zp = zp0 + (float)(g + q);
+            // part 1
+            const float uw = fmaf(zp, m[2], bu);
+            const float vw = fmaf(zp, m[6], bv);
+            const float w = fmaf(zp, m[10], bw);
+            float r = __builtin_amdgcn_rcpf(w);
+            if (WCHECK) r = (w > 0.0f) ? r : 0.0f;
+            const float u = uw * r;
+            const float v = vw * r;
+            r2[q] = r * r;
+            // part 2
+            au[q] = __builtin_amdgcn_fractf(u);
+            av[q] = __builtin_amdgcn_fractf(v);
+            const int iu = cvt_floor(CLAMP ? __builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u) : u);
+            const int iv = cvt_floor(CLAMP ? __builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v) : v);
+            const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * kElem + centre_bytes;
+            if constexpr (kIsF32)
+                load_taps<LAYOUT>(TT{}, rsrc, off, row_bytes, tl[q], tr[q], bl[q], br[q]);
+            else
+                raw[q] = load_taps16<LAYOUT>(rsrc, off, row_bytes);
+        }
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            // part 3
+            float fx;
+            if constexpr (kIsF32) {
+                const float top = fmaf(au[q], tr[q] - tl[q], tl[q]);
+                const float bot = fmaf(au[q], br[q] - bl[q], bl[q]);
+                fx = fmaf(av[q], bot - top, top);
+            } else {
+                fx = bilerp16<LAYOUT>(TT{}, raw[q], au[q], av[q]);
+            }
+            acc[g + q] = fmaf(r2[q], fx, acc[g + q]);
+        }
+    }
+}
+
+// waves per SIMD the register budget is fitted to (512 VGPRs / 8 = 64)
+#ifndef FDK_MIN_WAVES
+#define FDK_MIN_WAVES 8
+#endif
+template <typename TT, int LAYOUT, bool WCHECK>
+__global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused_kernel(const FusedArgs A)
+{
+    using E = typename TT::elem;
+    constexpr uint32_t kElem = sizeof(E) * (LAYOUT == kRows ? 1 : LAYOUT == kPairs ? 2 : 4);
     int bid = blockIdx.x;
     if (A.xcd_remap) {
         const int per = gridDim.x >> 3;
         bid = (bid & 7) * per + (bid >> 3);
     }
-    const int tx = bid % A.tiles_x;
-    const int rest = bid / A.tiles_x;
-    const int ty = rest % A.tiles_y;
-    const int zc = rest / A.tiles_y;
+    // Workgroups that run at the same time on one XCD share its L2; they
+    // are consecutive in this order, so stepping along the axis closest to
+    // the batch's ray direction keeps their projections on a view compact.
+    const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int tx = A.y_fastest ? t1 : t0;
+    const int ty = A.y_fastest ? t0 : t1;
 
-    const int x = tx * kFusedTile + (threadIdx.x & (kFusedTile - 1));
-    const int y = ty * kFusedTile + (threadIdx.x / kFusedTile);
+    // each 64-lane wave covers a kWaveX x kWaveY patch of columns
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wx0 = tx * kTileX;
+    const int wy0 = ty * kTileY + wave * kWaveY;
+    const int x = wx0 + (lane % kWaveX);
+    const int y = wy0 + (lane / kWaveX);
     const int zl0 = zc * kFusedZ;  // first z of this thread, relative to z_first
     const float xp = (float)x - A.c;
     const float yp = (float)y - A.c;
     const float zp0 = (float)(A.z_first + zl0) - A.c;
 
+    // Lanes 0..7 hold the corners of the wave's kWaveX x kWaveY x kFusedZ
+    // voxel box.  With w > 0 on the box, every voxel projects inside the
+    // hull of the corner projections, which decides per view whether the
+    // whole wave misses the detector (its taps are all zero: skip the view,
+    // the paper's clipping of Section 3.3) or stays inside the zero border
+    // (no clamping needed).  A 0.5 pixel margin absorbs rounding.
+    const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
+    const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
+    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
+    const bool corner_lane = lane < 8;
+
     float acc[kFusedZ];
 #pragma unroll
     for (int i = 0; i < kFusedZ; ++i) acc[i] = 0.0f;
 
-    const int Wp = A.Wp;
-    const uint32_t row_bytes = (uint32_t)Wp * sizeof(E);
-    const uint32_t plane_bytes = (uint32_t)(A.plane * (long long)sizeof(E));
-    const uint32_t centre_bytes = (uint32_t)A.origin_off * sizeof(E);
-    const E* plane = (const E*)A.img;
-    for (int j = 0; j < A.count; ++j, plane += A.plane) {
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
+    const uint32_t plane_bytes = (uint32_t)(A.plane * (long long)kElem);
+    const char* plane = (const char*)A.img;
+    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
         const float* m = A.m[j];
-        const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
-        const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
-        const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
-#pragma unroll
-        for (int g = 0; g < kFusedZ; g += kGroup) {
-            float au[kGroup], av[kGroup], r2[kGroup];
-            float tl[kGroup], tr[kGroup], bl[kGroup], br[kGroup];
-#pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const float zp = zp0 + (float)(g + q);
-                // part 1
-                const float uw = fmaf(zp, m[2], bu);
-                const float vw = fmaf(zp, m[6], bv);
-                const float w = fmaf(zp, m[10], bw);
-                float r = __builtin_amdgcn_rcpf(w);
-                if (WCHECK) r = (w > 0.0f) ? r : 0.0f;
-                const float u = uw * r;
-                const float v = vw * r;
-                r2[q] = r * r;
-                // part 2
-                au[q] = __builtin_amdgcn_fractf(u);
-                av[q] = __builtin_amdgcn_fractf(v);
-                const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
-                const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
-                const uint32_t off =
-                    (uint32_t)mad_i24(iv, Wp, iu) * (uint32_t)sizeof(E) + centre_bytes;
-                load_pair_buf(TT{}, rsrc, off, 0, tl[q], tr[q]);
-                load_pair_buf(TT{}, rsrc, off, row_bytes, bl[q], br[q]);
-            }
-#pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                // part 3
-                const float top = fmaf(au[q], tr[q] - tl[q], tl[q]);
-                const float bot = fmaf(au[q], br[q] - bl[q], bl[q]);
-                const float fx = fmaf(av[q], bot - top, top);
-                acc[g + q] = fmaf(r2[q], fx, acc[g + q]);
-            }
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
+        if constexpr (WCHECK) {
+            accumulate_view<TT, LAYOUT, WCHECK, true>(A, m, xp, yp, zp0, rsrc, acc);
+        } else {
+            const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
+            const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
+            const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
+            const float cr = __builtin_amdgcn_rcpf(cw);
+            const float u = cu * cr, v = cv * cr;
+            if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
+                __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
+                continue;
+            accumulate_view<TT, LAYOUT, false, true>(A, m, xp, yp, zp0, rsrc, acc);
         }
     }
 
@@ -220,23 +348,35 @@ __global__ __launch_bounds__(256) void bp_fused_kernel(const FusedArgs A)
     }
 }
 
-hipError_t launch_fused(const FusedArgs& a, int storage, bool wcheck, hipStream_t s)
+template <typename TT, int LAYOUT>
+static void launch_fused_t(const FusedArgs& a, bool wcheck, hipStream_t s)
 {
     dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
-#define FDK_LAUNCH(TT)                                                              \
-    do {                                                                            \
-        if (wcheck)                                                                 \
-            hipLaunchKernelGGL((bp_fused_kernel<TT, true>), grid, dim3(256), 0, s, a);  \
-        else                                                                        \
-            hipLaunchKernelGGL((bp_fused_kernel<TT, false>), grid, dim3(256), 0, s, a); \
-    } while (0)
-    if (storage == kF32)
-        FDK_LAUNCH(TF32);
-    else if (storage == kF16)
-        FDK_LAUNCH(TF16);
+    if (wcheck)
+        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, true>), grid, dim3(kThreads), 0, s, a);
     else
-        FDK_LAUNCH(TBF16);
-#undef FDK_LAUNCH
+        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false>), grid, dim3(kThreads), 0, s, a);
+}
+
+template <typename TT>
+static void launch_fused_l(const FusedArgs& a, int layout, bool wcheck, hipStream_t s)
+{
+    if (layout == kRows)
+        launch_fused_t<TT, kRows>(a, wcheck, s);
+    else if (layout == kPairs)
+        launch_fused_t<TT, kPairs>(a, wcheck, s);
+    else
+        launch_fused_t<TT, kQuads>(a, wcheck, s);
+}
+
+hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, hipStream_t s)
+{
+    if (storage == kF32)
+        launch_fused_l<TF32>(a, layout, wcheck, s);
+    else if (storage == kF16)
+        launch_fused_l<TF16>(a, layout, wcheck, s);
+    else
+        launch_fused_l<TBF16>(a, layout, wcheck, s);
     return hipGetLastError();
 }
 

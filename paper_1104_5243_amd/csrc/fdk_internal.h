@@ -18,6 +18,15 @@ constexpr int kPad = 2;
 
 enum StorageType { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
+// Staged plane layouts.  Element (r, c) of a plane holds, for the
+// zero-extended pixel value p(r, c) of the padded view:
+//   kRows : p(r, c)                                   (1 value)
+//   kPairs: p(r, c), p(r+1, c)                         (2 values)
+//   kQuads: p(r, c), p(r, c+1), p(r+1, c), p(r+1, c+1) (4 values)
+// so that the four taps of a bilinear sample are two loads (rows) or one
+// load (pairs: 2 adjacent elements; quads: 1 element).
+enum Layout { kRows = 0, kPairs = 1, kQuads = 2 };
+
 // Arguments of the fused kernel.  Matrices are in the centred index frame:
 // for voxel (x, y, z) with x' = x - c (likewise y', z'), (u'w, v'w, w) =
 // m * (x', y', z', 1), and the pixel coordinate is u = u' + ku.
@@ -31,11 +40,17 @@ struct FusedArgs {
     int Wp;              // staged row pitch (elements)
     float lo_u, hi_u;    // clamp range of u' before the floor
     float lo_v, hi_v;
+    // per-wave tests on the projected corners of a wave's voxel box (u', v'):
+    // all below skip_lo or all above skip_hi -> every tap is outside the
+    // detector; all within [in_lo, skip_hi] -> no tap leaves the zero border
+    float skip_lo_u, skip_hi_u, skip_lo_v, skip_hi_v;
+    float in_lo_u, in_lo_v;
     int origin_off;      // element offset of pixel (ku, kv) inside a plane
     float c;             // (N-1)/2
     int count;           // views in this batch
     int tiles_x, tiles_y, zchunks;
     int xcd_remap;       // 1: spread consecutive tiles over XCD-local ranges
+    int y_fastest;       // 1: consecutive workgroups step along y, else along x
     float m[kMaxBatch][12];
 };
 
@@ -55,15 +70,30 @@ struct StageArgs {
     void* dst;           // count planes of Hp*Wp elements
     int H, W, Hp, Wp;
     int count;
+    int layout;
 };
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s);
-hipError_t launch_fused(const FusedArgs& a, int storage, bool wcheck, hipStream_t s);
+hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, hipStream_t s);
 hipError_t launch_update_probe(float* a, size_t n, float s, hipStream_t st);
 
-constexpr int kFusedZ = 16;      // z voxels per thread in the fused kernel
-constexpr int kFusedTile = 16;   // x and y columns per 256-thread workgroup
+#ifndef FDK_FUSED_Z
+#define FDK_FUSED_Z 16
+#endif
+constexpr int kFusedZ = FDK_FUSED_Z;  // z voxels per thread in the fused kernel
+// A wave covers kWaveX x kWaveY voxel columns; a workgroup stacks kWgWaves
+// waves along y.
+#ifndef FDK_WG_WAVES
+#define FDK_WG_WAVES 4
+#endif
+#ifndef FDK_WAVE_X
+#define FDK_WAVE_X 8
+#endif
+constexpr int kWaveX = FDK_WAVE_X, kWaveY = 64 / FDK_WAVE_X;
+constexpr int kWgWaves = FDK_WG_WAVES;
+constexpr int kTileX = kWaveX, kTileY = kWaveY * kWgWaves;
+constexpr int kThreads = 64 * kWgWaves;
 
 }  // namespace fdk

@@ -1,0 +1,117 @@
+"""Reduced-precision projection storage (FP16 / BF16) and the large volume.
+
+FP32 arithmetic and accumulation throughout; only the stored projections
+are rounded.  Errors are measured against the FP64 oracle on the FP32
+stack, so storage quantisation counts as error.  Targets: FP16 storage
+relative RMSE <= 1e-3; BF16 (8 significand bits) is held to the same bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_1104_5243_amd as fdk
+    fdk.lib()
+    dev = torch.device("cuda:0")
+    geom, ell, _, _, _ = synth.workload("fdk128")
+    print(f"\n[stack] {geom.n_views} views {geom.W}x{geom.H}", flush=True)
+    proj = synth.filtered_projections(geom, ell)
+    return torch, fdk, dev, geom, proj, torch.from_numpy(proj).to(dev)
+
+
+@pytest.mark.parametrize("dtype_name", ["float16", "bfloat16"])
+def test_reduced_storage_parity_128(env, dtype_name):
+    torch, fdk, dev, geom, proj, proj_d = env
+    dtype = getattr(torch, dtype_name)
+    N = 128
+    vs, o = synth.volume_frame(N)
+    stack, scale = fdk.to_storage(proj_d, dtype)
+    vol = torch.zeros(N, N, N, device=dev)
+    fdk.backproject(vol, stack, geom.P, vs, o, view_scale=scale)
+    torch.cuda.synchronize()
+    ref = oracle.backproject(proj, geom.P, N, vs, o)
+    err = oracle.rel_rmse(vol.cpu().numpy(), ref)
+    print(f"{dtype_name} storage 128^3: relRMSE {err:.3e} PSNR "
+          f"{oracle.psnr(vol.cpu().numpy(), ref):.1f} dB", flush=True)
+    assert err <= 1e-3
+
+
+def test_power_of_four_view_scale_is_exact(env):
+    torch, fdk, dev, geom, proj, proj_d = env
+    N = 48
+    vs, o = synth.volume_frame(N)
+    a = torch.zeros(N, N, N, device=dev)
+    fdk.backproject(a, proj_d[:40], geom.P[:40], vs, o)
+    b = torch.zeros(N, N, N, device=dev)
+    k = np.arange(40) % 5 - 2  # scales 4^-2 .. 4^2
+    scaled = proj_d[:40] * torch.from_numpy(4.0 ** k).float().to(dev)[:, None, None]
+    fdk.backproject(b, scaled, geom.P[:40], vs, o, view_scale=(4.0 ** -k).astype(np.float32))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_fp16_sign_and_range_handling(env):
+    """Views of very different magnitudes, both signs, each scaled into
+    FP16's range separately."""
+    torch, fdk, dev, geom, proj, proj_d = env
+    N = 40
+    vs, o = synth.volume_frame(N)
+    mags = torch.tensor([1e-7, 1e-3, 10.0, 3e3] * 5, device=dev)
+    sign = torch.tensor([1.0, -1.0] * 10, device=dev)
+    p32 = proj_d[:20] * (mags * sign)[:, None, None] / proj_d[:20].abs().amax()
+    stack, scale = fdk.to_storage(p32, torch.float16)
+    assert torch.isfinite(stack.float()).all()
+    vol = torch.zeros(N, N, N, device=dev)
+    fdk.backproject(vol, stack, geom.P[:20], vs, o, view_scale=scale)
+    torch.cuda.synchronize()
+    ref = oracle.backproject(p32.cpu().numpy(), geom.P[:20], N, vs, o)
+    assert oracle.rel_rmse(vol.cpu().numpy(), ref) <= 1e-3
+
+
+@pytest.mark.parametrize("dtype_name", ["float32", "float16", "bfloat16"])
+def test_1024_sub_blocks(env, dtype_name):
+    """1024^3 (4 GiB accumulator, 64-bit addressing) with FP32, FP16 or
+    BF16 storage; the oracle checks the centre block [448,576)^3 and an
+    edge block [64,192) x [448,576) x [64,192) (x, y, z)."""
+    torch, fdk, dev, geom, proj, proj_d = env
+    N = 1024
+    vs, o = synth.volume_frame(N)
+    dtype = getattr(torch, dtype_name)
+    stack, scale = fdk.to_storage(proj_d, dtype)
+    vol = torch.zeros(N, N, N, device=dev)
+    fdk.backproject(vol, stack, geom.P, vs, o, view_scale=scale)
+    torch.cuda.synchronize()
+    blocks = [((448, 128), (448, 128), (448, 128)), ((64, 128), (448, 128), (64, 128))]
+    num = den = 0.0
+    for box in blocks:
+        (x0, nx), (y0, ny), (z0, nz) = box
+        ref = _ref_1024(proj, geom, box)
+        got = vol[z0:z0 + nz, y0:y0 + ny, x0:x0 + nx].double().cpu().numpy()
+        e = oracle.rel_rmse(got, ref)
+        print(f"  {dtype_name} 1024^3 block {box}: relRMSE {e:.3e}", flush=True)
+        num += float(np.sum((got - ref) ** 2))
+        den += float(np.sum(ref ** 2))
+    err = (num / den) ** 0.5
+    print(f"{dtype_name} 1024^3 sub-blocks: relRMSE {err:.3e}", flush=True)
+    # the centre block straddles the 2 GiB byte offset of the 4 GiB volume
+    assert err <= (1e-5 if dtype_name == "float32" else 1e-3)
+    del vol
+
+
+_REF = {}
+
+
+def _ref_1024(proj, geom, box):
+    if box not in _REF:
+        vs, o = synth.volume_frame(1024)
+        print(f"[oracle] 1024^3 block {box}", flush=True)
+        _REF[box] = oracle.backproject(proj, geom.P, 1024, vs, o, box=box)
+    return _REF[box]
