@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import math
+import re
 import os
 import sys
 import time
@@ -37,7 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # 1248x960, 2-socket Xeon X5670 (Westmere EP), all optimisations
 PAPER_GUPS = 3.79
 KERNEL_SRC = os.path.join(ROOT, "paper_1104_5243_amd", "csrc", "bp_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bp_fused_fdk512_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bp_fused_fdk512_traffic.txt")
 
 
 def log(msg: str) -> None:
@@ -45,19 +46,29 @@ def log(msg: str) -> None:
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the kernel source's code (comments and blank lines removed),
+    so that the recorded counter traffic stays tied to the code measured."""
+    text = open(KERNEL_SRC).read()
+    text = re.sub(r"//[^\n]*", "", text)
+    code = "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def measured_traffic():
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    counter summary, or None if the kernel source changed since."""
+    """HBM bytes per launch of the fused FP32 kernel from the committed
+    rocprofv3 counter summary, or None if the kernel source changed since."""
+    rec = {}
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
+        for line in open(TRAFFIC_FILE):
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.strip()
+    except OSError:
         return None
-    if rec.get("kernel_sha") != kernel_hash():
+    if rec.get("kernel_sha") != kernel_hash() or "hbm_bytes_per_launch" not in rec:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return int(float(rec["hbm_bytes_per_launch"]))
 
 
 def main() -> int:
@@ -72,7 +83,7 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain comparison, oracle sample and CPU baseline "
                          "(for profiler runs)")
-    ap.add_argument("--cpu-slices", type=int, default=24,
+    ap.add_argument("--cpu-slices", type=int, default=128,
                     help="z slices of the 512^3 volume in the CPU-baseline sample")
     ap.add_argument("--probe-hbm", action="store_true",
                     help="also run the update benchmark a[i] = s*a[i] over 2 GiB")
@@ -139,7 +150,8 @@ def main() -> int:
     # its mean duration (HIP events on the launch stream)
     kernel_s = kernel_ms / 1e3
     achieved_tflops = FLOP_PER_UPDATE * updates * args.steps / kernel_s / 1e12
-    traffic = measured_traffic()
+    traffic = (measured_traffic() if args.kernel == "fused" and args.storage == "f32"
+               and args.workload == "fdk512" else None)
     roofline = {
         "bound": "alu",
         "achieved": round(achieved_tflops, 3),

@@ -63,7 +63,7 @@ extern "C" {
 /*
  * fdk_backproject - FP32 backprojection of n_views projections.
  * Paper Section 3.1 (Listing 1), with the zero-padded projection buffers of
- * Section 3.3 and the image-loop blocking of Section 6.3: views are taken in
+ * Section 3.3 and the image-loop blocking of Section 6.2: views are taken in
  * batches, each batch staged into zero-padded buffers and backprojected in
  * one pass that keeps the voxel sums in registers.
  *   volume      device float[N^3], accumulated (+=)
@@ -86,9 +86,10 @@ int fdk_backproject(float* volume, int N, float voxel_size, const float origin[3
  *   proj_stack  device, n_views*H*W elements of proj_dtype (FDK_DTYPE_*):
  *               FP16 and BF16 are IEEE binary16 / bfloat16 bit patterns.
  *   view_scale  host float[n_views] or NULL: view i's pixel values are
- *               multiplied by view_scale[i] (applied exactly when it is a
- *               power of 4, by folding into the matrix; otherwise as an FP32
- *               multiply).  Lets FP16 stacks be stored pre-scaled into range.
+ *               multiplied by view_scale[i] > 0.  Applied by folding
+ *               1/sqrt(view_scale[i]) into the matrix in FP64 before its one
+ *               rounding to FP32, so a power of 4 is applied exactly.  Lets
+ *               FP16 stacks be stored pre-scaled into range.
  *   flags       FDK_KERNEL_FUSED or FDK_KERNEL_PLAIN (the plain kernel
  *               accepts FP32 only and no view_scale).
  * All arithmetic and the accumulation are FP32 whatever the storage type.

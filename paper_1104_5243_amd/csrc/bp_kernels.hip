@@ -4,7 +4,7 @@
 //   kFusedZ consecutive z voxels; the views of a batch are fused in one
 //   pass with the kFusedZ voxel sums held in registers, so the volume is
 //   read and written once per batch (the image-loop blocking of the paper's
-//   Section 6.3, with registers in place of the L1-resident voxel line).
+//   Section 6.2, with registers in place of the L1-resident voxel line).
 //   Per (voxel, view) the work is the paper's three parts (Section 3.2):
 //     part 1: (u'w, v'w, w) by three FMAs from a per-column base, one
 //             reciprocal r = 1/w, u' = u'w r, v' = v'w r;
