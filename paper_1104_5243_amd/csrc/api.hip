@@ -213,27 +213,13 @@ int acquire_staging(size_t bytes, hipStream_t stream, Staging** out)
     return FDK_OK;
 }
 
-int run_fused(float* volume, int N, float voxel_size, const float* origin, const void* proj,
-              int dtype, int n_views, int H, int W, const double* P, const float* view_scale,
-              hipStream_t stream)
+// Launch geometry shared by the backprojection and the forward projection:
+// everything in FusedArgs except the staged planes and the matrices.
+void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long long plane)
 {
     const int ku = (W - 1) / 2, kv = (H - 1) / 2;
-    const int Hp = H + 2 * kPad;
-    const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
-    const size_t esz = storage_size(dtype);
-    const int layout = g_layout;
-    const size_t elem = esz * (layout == kRows ? 1 : layout == kPairs ? 2 : 4);
-    const size_t plane_bytes = (size_t)Hp * Wp * elem;
-    if (plane_bytes >= (size_t(1) << 31))
-        return fail(FDK_ERR_UNSUPPORTED, "staged view of %zu bytes exceeds 2 GiB", plane_bytes);
-    int batch = g_batch;
-    if ((size_t)batch * plane_bytes > kMaxStagingBytes)
-        batch = (int)std::max<size_t>(1, kMaxStagingBytes / plane_bytes);
-    batch = std::min(batch, n_views);
-
-    FusedArgs A = {};
     A.vol = volume;
-    A.plane = (long long)Hp * Wp;
+    A.plane = plane;
     A.N = N;
     A.nz = N;
     A.z_first = 0;
@@ -257,6 +243,53 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     A.zchunks = (N + kFusedZ - 1) / kFusedZ;
     const long long blocks = (long long)A.tiles_x * A.tiles_y * A.zchunks;
     A.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+}
+
+// Fold the matrices of views [v0, v0+cnt) into A.m; returns whether some
+// voxel may have w <= 0, and sets the workgroup order from the batch's mean
+// ray direction.
+bool fold_batch(FusedArgs& A, const double* P, const float* view_scale, int v0, int cnt, int N,
+                float voxel_size, const float* origin, int H, int W)
+{
+    const int ku = (W - 1) / 2, kv = (H - 1) / 2;
+    const double c = 0.5 * (N - 1);
+    bool wcheck = false;
+    double ray[3] = {0.0, 0.0, 0.0};
+    A.count = cnt;
+    for (int j = 0; j < cnt; ++j) {
+        double lambda = 1.0;
+        if (view_scale) lambda = 1.0 / std::sqrt((double)view_scale[v0 + j]);
+        double Q[12];
+        fold_matrix(P + 12 * (size_t)(v0 + j), N, voxel_size, origin, ku, kv, lambda, Q);
+        wcheck |= needs_wcheck(Q, c);
+        for (int k = 0; k < 12; ++k) A.m[j][k] = (float)Q[k];
+        double d[3];
+        source_direction(Q, d);
+        for (int k = 0; k < 3; ++k) ray[k] += std::fabs(d[k]);
+    }
+    A.y_fastest = ray[1] > ray[0] ? 1 : 0;
+    return wcheck;
+}
+
+int run_fused(float* volume, int N, float voxel_size, const float* origin, const void* proj,
+              int dtype, int n_views, int H, int W, const double* P, const float* view_scale,
+              hipStream_t stream)
+{
+    const int Hp = H + 2 * kPad;
+    const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
+    const size_t esz = storage_size(dtype);
+    const int layout = g_layout;
+    const size_t elem = esz * (layout == kRows ? 1 : layout == kPairs ? 2 : 4);
+    const size_t plane_bytes = (size_t)Hp * Wp * elem;
+    if (plane_bytes >= (size_t(1) << 31))
+        return fail(FDK_ERR_UNSUPPORTED, "staged view of %zu bytes exceeds 2 GiB", plane_bytes);
+    int batch = g_batch;
+    if ((size_t)batch * plane_bytes > kMaxStagingBytes)
+        batch = (int)std::max<size_t>(1, kMaxStagingBytes / plane_bytes);
+    batch = std::min(batch, n_views);
+
+    FusedArgs A = {};
+    setup_args(A, volume, N, H, W, Wp, (long long)Hp * Wp);
 
     std::lock_guard<std::mutex> lock(g_stage_mu);
     Staging* st = nullptr;
@@ -264,7 +297,6 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     if (rc != FDK_OK) return rc;
     A.img = st->ptr;
 
-    const double c = 0.5 * (N - 1);
     for (int v0 = 0; v0 < n_views; v0 += batch) {
         const int cnt = std::min(batch, n_views - v0);
         StageArgs S;
@@ -278,27 +310,60 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
         S.layout = layout;
         hipError_t e = launch_stage(S, dtype, stream);
         if (e != hipSuccess) return hip_fail(e, "stage launch");
-
-        bool wcheck = false;
-        A.count = cnt;
-        double ray[3] = {0.0, 0.0, 0.0};
-        for (int j = 0; j < cnt; ++j) {
-            double lambda = 1.0;
-            if (view_scale) lambda = 1.0 / std::sqrt((double)view_scale[v0 + j]);
-            double Q[12];
-            fold_matrix(P + 12 * (size_t)(v0 + j), N, voxel_size, origin, ku, kv, lambda, Q);
-            wcheck |= needs_wcheck(Q, c);
-            for (int k = 0; k < 12; ++k) A.m[j][k] = (float)Q[k];
-            double d[3];
-            source_direction(Q, d);
-            for (int k = 0; k < 3; ++k) ray[k] += std::fabs(d[k]);
-        }
-        A.y_fastest = ray[1] > ray[0] ? 1 : 0;
+        const bool wcheck = fold_batch(A, P, view_scale, v0, cnt, N, voxel_size, origin, H, W);
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
         e = launch_fused(A, dtype, layout, wcheck, stream);
         if (e != hipSuccess) return hip_fail(e, "backprojection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
+    }
+    hipError_t e = hipEventRecord(st->last_use, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return FDK_OK;
+}
+
+int run_forward(float* proj, int n_views, int H, int W, const double* P, const float* volume,
+                int N, float voxel_size, const float* origin, hipStream_t stream)
+{
+    const int Hp = H + 2 * kPad;
+    const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
+    const size_t plane_bytes = (size_t)Hp * Wp * 4;
+    if (plane_bytes >= (size_t(1) << 31))
+        return fail(FDK_ERR_UNSUPPORTED, "padded view of %zu bytes exceeds 2 GiB", plane_bytes);
+    int batch = g_batch;
+    if ((size_t)batch * plane_bytes > kMaxStagingBytes)
+        batch = (int)std::max<size_t>(1, kMaxStagingBytes / plane_bytes);
+    batch = std::min(batch, n_views);
+
+    FusedArgs A = {};
+    setup_args(A, const_cast<float*>(volume), N, H, W, Wp, (long long)Hp * Wp);
+
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    Staging* st = nullptr;
+    int rc = acquire_staging((size_t)batch * plane_bytes, stream, &st);
+    if (rc != FDK_OK) return rc;
+    A.img = st->ptr;
+
+    for (int v0 = 0; v0 < n_views; v0 += batch) {
+        const int cnt = std::min(batch, n_views - v0);
+        hipError_t e = launch_zero((float*)st->ptr, (size_t)cnt * Hp * Wp, stream);
+        if (e != hipSuccess) return hip_fail(e, "zero launch");
+        const bool wcheck = fold_batch(A, P, nullptr, v0, cnt, N, voxel_size, origin, H, W);
+        hipEvent_t t0;
+        if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
+        e = launch_scatter(A, wcheck, stream);
+        if (e != hipSuccess) return hip_fail(e, "forward projection launch");
+        if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
+        UnstageArgs U;
+        U.planes = (const float*)st->ptr;
+        U.dst = proj + (size_t)v0 * H * W;
+        U.H = H;
+        U.W = W;
+        U.Hp = Hp;
+        U.Wp = Wp;
+        U.count = cnt;
+        e = launch_unstage_add(U, stream);
+        if (e != hipSuccess) return hip_fail(e, "unstage launch");
     }
     hipError_t e = hipEventRecord(st->last_use, stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -385,9 +450,11 @@ int fdk_forward_project(float* proj_stack, int n_views, int H, int W, const doub
                         void* stream)
 {
     g_err.clear();
-    (void)proj_stack; (void)n_views; (void)H; (void)W; (void)P_mats; (void)volume; (void)N;
-    (void)voxel_size; (void)origin; (void)stream;
-    return fail(FDK_ERR_UNSUPPORTED, "fdk_forward_project is not built yet");
+    if (!proj_stack && n_views > 0) return fail(FDK_ERR_INVALID_ARG, "proj_stack is NULL");
+    int rc = validate_common(volume, N, voxel_size, origin, proj_stack, n_views, H, W, P_mats);
+    if (rc != FDK_OK || n_views == 0) return rc;
+    return run_forward(proj_stack, n_views, H, W, P_mats, volume, N, voxel_size, origin,
+                       (hipStream_t)stream);
 }
 
 int fdk_update_probe(float* a, size_t n, float s, void* stream)

@@ -381,6 +381,144 @@ hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck
 }
 
 // ---------------------------------------------------------------------------
+// forward projection: the exact transpose of the backprojection
+// ---------------------------------------------------------------------------
+// Every voxel value times r^2 = 1/w^2 is spread onto the four taps the
+// backprojection reads, with the same bilinear weights (1-au)(1-av), au(1-av),
+// (1-au)av, au av.  The targets are padded FP32 planes (rows layout): taps
+// outside the detector land in the 2-pixel border and are dropped when the
+// interior is added to the caller's stack.  Float atomics make the order of
+// the sums, and so their last bits, vary between runs.
+template <bool WCHECK>
+__global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
+{
+    int bid = blockIdx.x;
+    if (A.xcd_remap) {
+        const int per = gridDim.x >> 3;
+        bid = (bid & 7) * per + (bid >> 3);
+    }
+    const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int tx = A.y_fastest ? t1 : t0;
+    const int ty = A.y_fastest ? t0 : t1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wx0 = tx * kTileX;
+    const int wy0 = ty * kTileY + wave * kWaveY;
+    const int x = wx0 + (lane % kWaveX);
+    const int y = wy0 + (lane / kWaveX);
+    const int zl0 = zc * kFusedZ;
+    const float xp = (float)x - A.c;
+    const float yp = (float)y - A.c;
+    const float zp0 = (float)(A.z_first + zl0) - A.c;
+    const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
+    const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
+    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
+    const bool corner_lane = lane < 8;
+
+    // the thread's voxel values (0 outside the volume)
+    float val[kFusedZ];
+    const bool inside = x < A.N && y < A.N;
+    const size_t slice = (size_t)A.N * A.N;
+    const float* src = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
+#pragma unroll
+    for (int i = 0; i < kFusedZ; ++i)
+        val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
+
+    const int Wp = A.Wp;
+    const uint32_t row_bytes = (uint32_t)Wp * 4u;
+    const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
+    const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
+    const char* plane = (const char*)A.img;
+    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
+        const float* m = A.m[j];
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
+        if constexpr (!WCHECK) {
+            const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
+            const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
+            const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
+            const float cr = __builtin_amdgcn_rcpf(cw);
+            const float u = cu * cr, v = cv * cr;
+            if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
+                __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
+                continue;
+        }
+        const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
+        const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
+        const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
+#pragma unroll
+        for (int i = 0; i < kFusedZ; ++i) {
+            const float zp = zp0 + (float)i;
+            const float uw = fmaf(zp, m[2], bu);
+            const float vw = fmaf(zp, m[6], bv);
+            const float w = fmaf(zp, m[10], bw);
+            float r = __builtin_amdgcn_rcpf(w);
+            if (WCHECK) r = (w > 0.0f) ? r : 0.0f;
+            const float u = uw * r;
+            const float v = vw * r;
+            const float au = __builtin_amdgcn_fractf(u);
+            const float av = __builtin_amdgcn_fractf(v);
+            const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
+            const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
+            const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
+            const float s = val[i] * (r * r);
+            const float b = s * av;       // bottom row weight
+            const float a = s - b;        // top row weight
+            const float tr = a * au, br = b * au;
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b - br, rsrc, off, row_bytes, 0);
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(br, rsrc, off + 4u, row_bytes, 0);
+        }
+    }
+}
+
+hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
+{
+    dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
+    if (wcheck)
+        hipLaunchKernelGGL((fp_scatter_kernel<true>), grid, dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((fp_scatter_kernel<false>), grid, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void unstage_add_kernel(UnstageArgs a)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    const int view = blockIdx.z;
+    if (j >= a.W) return;
+    const float v = a.planes[((size_t)view * a.Hp + k + kPad) * a.Wp + j + kPad];
+    a.dst[((size_t)view * a.H + k) * a.W + j] += v;
+}
+
+hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s)
+{
+    dim3 grid((a.W + 255) / 256, a.H, a.count);
+    hipLaunchKernelGGL(unstage_add_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(float4* a, size_t n4)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride)
+        a[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// n must be a multiple of 4 and a 16-byte aligned
+hipError_t launch_zero(float* a, size_t n, hipStream_t st)
+{
+    size_t blocks = (n / 4 + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)a, n / 4);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // plain
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void bp_plain_kernel(const PlainArgs A)

@@ -73,11 +73,23 @@ struct StageArgs {
     int layout;
 };
 
+// Padded FP32 accumulation planes of the forward projector (rows layout).
+struct UnstageArgs {
+    const float* planes;  // count planes of Hp*Wp floats, pixel (j, k) at (k+kPad)*Wp + j+kPad
+    float* dst;           // count views of H*W floats, accumulated
+    int H, W, Hp, Wp;
+    int count;
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s);
 hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, hipStream_t s);
 hipError_t launch_update_probe(float* a, size_t n, float s, hipStream_t st);
+hipError_t launch_zero(float* a, size_t n, hipStream_t st);
+// forward projection of a.vol into the padded planes at a.img (scatter)
+hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s);
+hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s);
 
 #ifndef FDK_FUSED_Z
 #define FDK_FUSED_Z 16
