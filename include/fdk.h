@@ -125,6 +125,25 @@ int fdk_forward_project(float* proj_stack, int n_views, int H, int W, const doub
                         void* stream);
 
 /*
+ * fdk_prefilter - the Feldkamp 2D pre-processing of line integrals on the
+ * GPU (the step before the backprojection, named in the paper's Section 1.1):
+ * for view i (source angle beta_i = beta0 + i*dbeta) and pixel (j, k) with
+ * detector offsets a = (j - (W-1)/2) pixel, b = (k - (H-1)/2) pixel (mm),
+ *   q = p * sdd / sqrt(sdd^2 + a^2 + b^2) * parker(beta_i, gamma_j)
+ * with gamma_j = -atan(a / sdd) and the Parker short-scan weight over
+ * pi + 2*delta (parker = 1/2 everywhere when delta < 0: full circle), then
+ * each row is convolved (linear convolution, zero outside the row) with the
+ * discrete Ram-Lak kernel h[0] = 1/(4 tau^2), h[odd n] = -1/(n pi tau)^2,
+ * h[even n] = 0 at the isocentre spacing tau = pixel * sid / sdd, and scaled
+ * by tau * dbeta (the angular step of the backprojection sum).
+ *   out, in     device float[n_views*H*W] (out is overwritten; distinct buffers)
+ *   all lengths in mm, angles in radians.
+ */
+int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double beta0,
+                  double dbeta, double delta, double sid, double sdd, double pixel,
+                  void* stream);
+
+/*
  * fdk_update_probe - the paper's update benchmark a[i] = s * a[i]
  * (Section 2) over n floats of device memory, used to measure the
  * achievable HBM bandwidth and to scale memory counters.

@@ -29,7 +29,7 @@ KERNEL_FUSED, KERNEL_PLAIN = 0, 1
 # every symbol include/fdk.h declares
 EXPORTS = (
     "fdk_backproject", "fdk_backproject_ex", "fdk_backproject_plain", "fdk_forward_project",
-    "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
+    "fdk_prefilter", "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
     "fdk_release", "fdk_last_error", "fdk_version",
 )
 
@@ -63,6 +63,8 @@ def lib():
         L.fdk_backproject_plain.argtypes = [vp, i, f, fp, vp, i, i, i, dp, vp]
         L.fdk_forward_project.argtypes = [vp, i, i, i, dp, vp, i, f, fp, vp]
         L.fdk_update_probe.argtypes = [vp, ctypes.c_size_t, f, vp]
+        d = ctypes.c_double
+        L.fdk_prefilter.argtypes = [vp, vp, i, i, i, d, d, d, d, d, d, vp]
         L.fdk_profile_begin.argtypes = []
         L.fdk_profile_end.argtypes = [dp, ctypes.POINTER(ctypes.c_int)]
         L.fdk_set_batch.argtypes = [i]
@@ -199,6 +201,25 @@ def forward_project(proj, volume, P, voxel_size: float, origin, stream=None):
             float(voxel_size), op, _stream_ptr(stream, volume.device))
     _check(rc)
     return proj
+
+
+def prefilter(out, proj, beta0: float, dbeta: float, delta: float, sid: float, sdd: float,
+              pixel: float, stream=None):
+    """Feldkamp pre-processing of line integrals on the GPU (cosine weight,
+    Parker weight over pi + 2*delta, or 1/2 for delta < 0, Ram-Lak row
+    filter, times tau * dbeta): out = filtered(proj), both (V, H, W) float32."""
+    import torch
+    _dev_tensor(proj, "proj", (torch.float32,), 3)
+    _dev_tensor(out, "out", (torch.float32,), 3)
+    if out.shape != proj.shape:
+        raise ValueError("out and proj must have the same shape")
+    V, H, W = proj.shape
+    with torch.cuda.device(proj.device):
+        rc = lib().fdk_prefilter(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(proj.data_ptr()),
+                                 V, H, W, float(beta0), float(dbeta), float(delta), float(sid),
+                                 float(sdd), float(pixel), _stream_ptr(stream, proj.device))
+    _check(rc)
+    return out
 
 
 def update_probe(a, s: float = 1.0000001, stream=None):

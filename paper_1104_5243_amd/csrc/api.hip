@@ -457,6 +457,41 @@ int fdk_forward_project(float* proj_stack, int n_views, int H, int W, const doub
                        (hipStream_t)stream);
 }
 
+int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double beta0,
+                  double dbeta, double delta, double sid, double sdd, double pixel,
+                  void* stream)
+{
+    g_err.clear();
+    if (n_views < 0) return fail(FDK_ERR_INVALID_ARG, "n_views=%d < 0", n_views);
+    if (H < 1 || W < 1 || W > 4000 || H > 32768)
+        return fail(FDK_ERR_INVALID_ARG, "detector %dx%d outside [1, 4000] x [1, 32768]", W, H);
+    if (n_views == 0) return FDK_OK;
+    if (!out || !in) return fail(FDK_ERR_INVALID_ARG, "out or in is NULL");
+    if (out == in) return fail(FDK_ERR_INVALID_ARG, "out and in must be distinct buffers");
+    if (!(std::isfinite(beta0) && std::isfinite(dbeta) && std::isfinite(delta)))
+        return fail(FDK_ERR_INVALID_ARG, "angles must be finite");
+    if (!(sid > 0.0 && sdd > 0.0 && pixel > 0.0 && std::isfinite(sid) && std::isfinite(sdd) &&
+          std::isfinite(pixel)))
+        return fail(FDK_ERR_INVALID_ARG, "sid, sdd and pixel must be finite and > 0");
+    if ((long long)n_views * H > 0x7fffffffLL)
+        return fail(FDK_ERR_INVALID_ARG, "too many rows");
+    PrefilterArgs A;
+    A.out = out;
+    A.in = in;
+    A.rows = n_views * H;
+    A.H = H;
+    A.W = W;
+    A.beta0 = beta0;
+    A.dbeta = dbeta;
+    A.delta = delta;
+    A.sdd = sdd;
+    A.pixel = pixel;
+    A.tau = pixel * sid / sdd;
+    A.scale = pixel * sid / sdd * dbeta;
+    hipError_t e = launch_prefilter(A, (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "prefilter launch");
+}
+
 int fdk_update_probe(float* a, size_t n, float s, void* stream)
 {
     g_err.clear();

@@ -81,6 +81,15 @@ struct UnstageArgs {
     int count;
 };
 
+struct PrefilterArgs {
+    float* out;
+    const float* in;
+    int rows, H, W;      // rows = n_views * H
+    double beta0, dbeta;
+    double delta, sdd, pixel, tau;
+    double scale;        // tau * dbeta
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s);
 hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, hipStream_t s);
@@ -90,6 +99,7 @@ hipError_t launch_zero(float* a, size_t n, hipStream_t st);
 // forward projection of a.vol into the padded planes at a.img (scatter)
 hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s);
 hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s);
+hipError_t launch_prefilter(const PrefilterArgs& a, hipStream_t s);
 
 #ifndef FDK_FUSED_Z
 #define FDK_FUSED_Z 16
