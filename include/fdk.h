@@ -144,6 +144,71 @@ int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double
                   void* stream);
 
 /*
+ * Kernels of the learned filter (training and inference).  The learned
+ * Feldkamp filter acts along detector rows: a long learned ramp, a per-view
+ * weight, and a small 1D CNN; these entry points are its building blocks.
+ * All tensors are device float32, rows of W samples, channel-major within a
+ * row: x[r][c][j] at ((r*channels + c)*W + j).  Outputs are overwritten unless
+ * stated.  Asynchronous on `stream`.
+ */
+#define FDK_CONV_RELU 1       /* max(0, .) on the result */
+#define FDK_CONV_ACCUMULATE 2 /* add the existing output before the ReLU */
+#define FDK_CONV_TRANSPOSE 4  /* the adjoint convolution (data gradient) */
+
+/*
+ * fdk_conv_rows - batched 1D convolution along rows with zero extension:
+ *   out[r][co][j] = bias[co] + sum_{ci < cin, t < K} w(co, ci, t) in[r][ci][j + t - pad]
+ * with w(co, ci, t) = weight[(co*cin + ci)*K + t], or with FDK_CONV_TRANSPOSE
+ * w(co, ci, t) = weight[(ci*cout + co)*K + K-1-t]: the adjoint of the
+ * convolution from `cout` to `cin` channels whose weight is `weight`, when
+ * called with pad = K-1-(that convolution's pad).  bias may be NULL.
+ * Limits: K <= 32 and cout <= 64, or cin = cout = 1 and K <= 8191.
+ */
+int fdk_conv_rows(float* out, const float* in, const float* weight, const float* bias, int rows,
+                  int W, int cin, int cout, int K, int pad, int flags, void* stream);
+
+/* Bytes of workspace fdk_conv_rows_wgrad needs for these sizes. */
+size_t fdk_conv_rows_wgrad_workspace(int cin, int cout, int K);
+
+/*
+ * fdk_conv_rows_wgrad - gradients of fdk_conv_rows (forward, no ReLU) with
+ * respect to its weight and bias, given dout = dL/dout:
+ *   dweight[(co*cin + ci)*K + t] = sum_r sum_j dout[r][co][j] in[r][ci][j + t - pad]
+ *   dbias[co] = sum_r sum_j dout[r][co][j]                 (dbias may be NULL)
+ * Accumulated in FP64 in a fixed order (deterministic), stored FP32.
+ * workspace: device memory of at least fdk_conv_rows_wgrad_workspace() bytes.
+ */
+int fdk_conv_rows_wgrad(float* dweight, float* dbias, const float* dout, const float* in, int rows,
+                        int W, int cin, int cout, int K, int pad, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* y[g][i] = x[g][i] * scale[g] (+ y[g][i] with accumulate != 0), i < group_len;
+   scale is device float[groups].  y may equal x. */
+int fdk_scale_groups(float* y, const float* x, const float* scale, size_t group_len, int groups,
+                     int accumulate, void* stream);
+
+/* out[g] = sum_i a[g][i] * b[g][i] (FP64 accumulation), device float[groups]. */
+int fdk_group_dot(float* out, const float* a, const float* b, size_t group_len, int groups,
+                  void* stream);
+
+/* dx = dy where y > 0 else 0 (ReLU backward; y is the ReLU's output). */
+int fdk_relu_backward(float* dx, const float* dy, const float* y, size_t n, void* stream);
+
+/* y = A x, or y = A^T x with transpose != 0; A device float[rows][cols]. */
+int fdk_matvec(float* y, const float* A, const float* x, int rows, int cols, int transpose,
+               void* stream);
+
+/* One Adam step (Kingma and Ba, 2015, with bias correction; step >= 1):
+   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr m^ / (sqrt(v^) + eps). */
+int fdk_adam(float* param, float* m, float* v, const float* grad, int n, float lr, float beta1,
+             float beta2, float eps, int step, void* stream);
+
+/* Mean squared error: loss[0] = mean((a - b)^2) (device float), and, if grad
+   is not NULL, grad = 2 (a - b) / n.  workspace: >= 8192 bytes of device memory. */
+int fdk_mse(float* grad, float* loss, const float* a, const float* b, size_t n, void* workspace,
+            size_t workspace_bytes, void* stream);
+
+/*
  * fdk_update_probe - the paper's update benchmark a[i] = s * a[i]
  * (Section 2) over n floats of device memory, used to measure the
  * achievable HBM bandwidth and to scale memory counters.

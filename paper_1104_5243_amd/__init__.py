@@ -29,7 +29,9 @@ KERNEL_FUSED, KERNEL_PLAIN = 0, 1
 # every symbol include/fdk.h declares
 EXPORTS = (
     "fdk_backproject", "fdk_backproject_ex", "fdk_backproject_plain", "fdk_forward_project",
-    "fdk_prefilter", "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
+    "fdk_prefilter", "fdk_conv_rows", "fdk_conv_rows_wgrad_workspace", "fdk_conv_rows_wgrad",
+    "fdk_scale_groups", "fdk_group_dot", "fdk_relu_backward", "fdk_matvec", "fdk_adam", "fdk_mse",
+    "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
     "fdk_release", "fdk_last_error", "fdk_version",
 )
 
@@ -65,6 +67,16 @@ def lib():
         L.fdk_update_probe.argtypes = [vp, ctypes.c_size_t, f, vp]
         d = ctypes.c_double
         L.fdk_prefilter.argtypes = [vp, vp, i, i, i, d, d, d, d, d, d, vp]
+        sz = ctypes.c_size_t
+        L.fdk_conv_rows.argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, i, vp]
+        L.fdk_conv_rows_wgrad_workspace.argtypes = [i, i, i]
+        L.fdk_conv_rows_wgrad.argtypes = [vp, vp, vp, vp, i, i, i, i, i, i, vp, sz, vp]
+        L.fdk_scale_groups.argtypes = [vp, vp, vp, sz, i, i, vp]
+        L.fdk_group_dot.argtypes = [vp, vp, vp, sz, i, vp]
+        L.fdk_relu_backward.argtypes = [vp, vp, vp, sz, vp]
+        L.fdk_matvec.argtypes = [vp, vp, vp, i, i, i, vp]
+        L.fdk_adam.argtypes = [vp, vp, vp, vp, i, f, f, f, f, i, vp]
+        L.fdk_mse.argtypes = [vp, vp, vp, vp, sz, vp, sz, vp]
         L.fdk_profile_begin.argtypes = []
         L.fdk_profile_end.argtypes = [dp, ctypes.POINTER(ctypes.c_int)]
         L.fdk_set_batch.argtypes = [i]
@@ -75,6 +87,7 @@ def lib():
         for name in EXPORTS:
             if name not in ("fdk_last_error",):
                 getattr(L, name).restype = ctypes.c_int
+        L.fdk_conv_rows_wgrad_workspace.restype = ctypes.c_size_t
         _lib = L
     return _lib
 
@@ -220,6 +233,99 @@ def prefilter(out, proj, beta0: float, dbeta: float, delta: float, sid: float, s
                                  float(sdd), float(pixel), _stream_ptr(stream, proj.device))
     _check(rc)
     return out
+
+
+# --------------------------------------------------------------------------
+# learned-filter kernels (thin wrappers; tensors are float32 CUDA tensors)
+# --------------------------------------------------------------------------
+CONV_RELU, CONV_ACCUMULATE, CONV_TRANSPOSE = 1, 2, 4
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(*ts):
+    import torch
+    for t in ts:
+        if t is not None:
+            _dev_tensor(t, "tensor", (torch.float32,))
+
+
+def conv_rows(out, x, weight, bias, rows, W, cin, cout, K, pad, flags=0, stream=None):
+    """out[r][co][j] = bias[co] + sum w(co,ci,t) x[r][ci][j+t-pad] (see fdk.h)."""
+    _f32(out, x, weight, bias)
+    with torch_device(x):
+        _check(lib().fdk_conv_rows(_p(out), _p(x), _p(weight), _p(bias), rows, W, cin, cout, K,
+                                   pad, flags, _stream_ptr(stream, x.device)))
+    return out
+
+
+def conv_rows_wgrad_workspace(cin, cout, K) -> int:
+    return int(lib().fdk_conv_rows_wgrad_workspace(cin, cout, K))
+
+
+def conv_rows_wgrad(dweight, dbias, dout, x, rows, W, cin, cout, K, pad, workspace, stream=None):
+    _f32(dweight, dbias, dout, x)
+    with torch_device(x):
+        _check(lib().fdk_conv_rows_wgrad(_p(dweight), _p(dbias), _p(dout), _p(x), rows, W, cin,
+                                         cout, K, pad, _p(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream_ptr(stream, x.device)))
+
+
+def scale_groups(y, x, scale, group_len, groups, accumulate=False, stream=None):
+    _f32(y, x, scale)
+    with torch_device(x):
+        _check(lib().fdk_scale_groups(_p(y), _p(x), _p(scale), group_len, groups,
+                                      1 if accumulate else 0, _stream_ptr(stream, x.device)))
+    return y
+
+
+def group_dot(out, a, b, group_len, groups, stream=None):
+    _f32(out, a, b)
+    with torch_device(a):
+        _check(lib().fdk_group_dot(_p(out), _p(a), _p(b), group_len, groups,
+                                   _stream_ptr(stream, a.device)))
+    return out
+
+
+def relu_backward(dx, dy, y, stream=None):
+    _f32(dx, dy, y)
+    with torch_device(y):
+        _check(lib().fdk_relu_backward(_p(dx), _p(dy), _p(y), y.numel(),
+                                       _stream_ptr(stream, y.device)))
+    return dx
+
+
+def matvec(y, A, x, rows, cols, transpose=False, stream=None):
+    _f32(y, A, x)
+    with torch_device(A):
+        _check(lib().fdk_matvec(_p(y), _p(A), _p(x), rows, cols, 1 if transpose else 0,
+                                _stream_ptr(stream, A.device)))
+    return y
+
+
+def adam(param, m, v, grad, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _f32(param, m, v, grad)
+    with torch_device(param):
+        _check(lib().fdk_adam(_p(param), _p(m), _p(v), _p(grad), param.numel(), float(lr),
+                              float(beta1), float(beta2), float(eps), int(step),
+                              _stream_ptr(stream, param.device)))
+
+
+def mse(grad, loss, a, b, workspace, stream=None):
+    """loss[0] = mean((a-b)^2); grad = 2 (a-b)/n if grad is not None."""
+    _f32(grad, loss, a, b)
+    with torch_device(a):
+        _check(lib().fdk_mse(_p(grad), _p(loss), _p(a), _p(b), a.numel(), _p(workspace),
+                             workspace.numel() * workspace.element_size(),
+                             _stream_ptr(stream, a.device)))
+
+
+def torch_device(t):
+    import torch
+    return torch.cuda.device(t.device)
 
 
 def update_probe(a, s: float = 1.0000001, stream=None):

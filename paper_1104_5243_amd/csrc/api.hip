@@ -492,6 +492,152 @@ int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double
     return e == hipSuccess ? FDK_OK : hip_fail(e, "prefilter launch");
 }
 
+int fdk_conv_rows(float* out, const float* in, const float* weight, const float* bias, int rows,
+                  int W, int cin, int cout, int K, int pad, int flags, void* stream)
+{
+    g_err.clear();
+    if (rows < 0 || W < 1 || cin < 1 || cout < 1 || K < 1)
+        return fail(FDK_ERR_INVALID_ARG, "bad sizes rows=%d W=%d cin=%d cout=%d K=%d", rows, W,
+                    cin, cout, K);
+    if (pad < 0 || pad >= K + W) return fail(FDK_ERR_INVALID_ARG, "pad=%d out of range", pad);
+    if (flags & ~(FDK_CONV_RELU | FDK_CONV_ACCUMULATE | FDK_CONV_TRANSPOSE))
+        return fail(FDK_ERR_INVALID_ARG, "unknown flags %d", flags);
+    const bool shortk = K <= 32 && cout <= 64 && cin <= 64;
+    const bool longk = cin == 1 && cout == 1 && K <= 8191;
+    if (!shortk && !longk)
+        return fail(FDK_ERR_UNSUPPORTED, "need K <= 32 and channels <= 64, or cin = cout = 1");
+    if (rows == 0) return FDK_OK;
+    if (!out || !in || !weight) return fail(FDK_ERR_INVALID_ARG, "out, in or weight is NULL");
+    if (out == in) return fail(FDK_ERR_INVALID_ARG, "out and in must be distinct");
+    if (rows > 65535) return fail(FDK_ERR_UNSUPPORTED, "rows=%d > 65535 per call", rows);
+    LearnConvArgs A;
+    A.out = out;
+    A.in = in;
+    A.weight = weight;
+    A.bias = bias;
+    A.rows = rows;
+    A.W = W;
+    A.cin = cin;
+    A.cout = cout;
+    A.K = K;
+    A.pad = pad;
+    A.relu = (flags & FDK_CONV_RELU) ? 1 : 0;
+    A.accumulate = (flags & FDK_CONV_ACCUMULATE) ? 1 : 0;
+    A.transpose = (flags & FDK_CONV_TRANSPOSE) ? 1 : 0;
+    hipError_t e = launch_conv(A, (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "conv launch");
+}
+
+size_t fdk_conv_rows_wgrad_workspace(int cin, int cout, int K)
+{
+    if (cin < 1 || cout < 1 || K < 1) return 0;
+    return (size_t)kGradBlocks * ((size_t)cin * cout * K + cout) * sizeof(double);
+}
+
+int fdk_conv_rows_wgrad(float* dweight, float* dbias, const float* dout, const float* in, int rows,
+                        int W, int cin, int cout, int K, int pad, void* workspace,
+                        size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    if (rows < 0 || W < 1 || cin < 1 || cout < 1 || K < 1)
+        return fail(FDK_ERR_INVALID_ARG, "bad sizes");
+    if (pad < 0 || pad >= K + W) return fail(FDK_ERR_INVALID_ARG, "pad=%d out of range", pad);
+    const bool longk = cin == 1 && cout == 1 && K > 32;
+    if (!longk && (long long)cin * cout * K > 10240)
+        return fail(FDK_ERR_UNSUPPORTED, "cin*cout*K > 10240");
+    if (longk && K > 8192) return fail(FDK_ERR_UNSUPPORTED, "K > 8192");
+    if (!dweight || !dout || !in || !workspace)
+        return fail(FDK_ERR_INVALID_ARG, "dweight, dout, in or workspace is NULL");
+    if (workspace_bytes < fdk_conv_rows_wgrad_workspace(cin, cout, K))
+        return fail(FDK_ERR_INVALID_ARG, "workspace of %zu bytes is too small", workspace_bytes);
+    if (longk && (size_t)(2 * W + K) * sizeof(float) > 65536)
+        return fail(FDK_ERR_UNSUPPORTED, "row too long for the LDS");
+    if (!longk && (size_t)(cout * 128 + cin * (128 + K - 1)) * sizeof(float) > 65536)
+        return fail(FDK_ERR_UNSUPPORTED, "channels too many for the LDS");
+    LearnGradArgs A;
+    A.dweight = dweight;
+    A.dbias = dbias;
+    A.dout = dout;
+    A.in = in;
+    A.part = (double*)workspace;
+    A.rows = rows;
+    A.W = W;
+    A.cin = cin;
+    A.cout = cout;
+    A.K = K;
+    A.pad = pad;
+    hipError_t e = longk ? launch_wgrad_long(A, kGradBlocks, (hipStream_t)stream)
+                         : launch_wgrad(A, kGradBlocks, (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "wgrad launch");
+}
+
+int fdk_scale_groups(float* y, const float* x, const float* scale, size_t group_len, int groups,
+                     int accumulate, void* stream)
+{
+    g_err.clear();
+    if (groups < 0) return fail(FDK_ERR_INVALID_ARG, "groups < 0");
+    if (groups == 0 || group_len == 0) return FDK_OK;
+    if (!y || !x || !scale) return fail(FDK_ERR_INVALID_ARG, "NULL pointer");
+    hipError_t e = launch_scale_groups(y, x, scale, group_len, groups, accumulate,
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "scale launch");
+}
+
+int fdk_group_dot(float* out, const float* a, const float* b, size_t group_len, int groups,
+                  void* stream)
+{
+    g_err.clear();
+    if (groups < 0 || groups > 0x7fffffff) return fail(FDK_ERR_INVALID_ARG, "bad groups");
+    if (groups == 0) return FDK_OK;
+    if (!out || !a || !b) return fail(FDK_ERR_INVALID_ARG, "NULL pointer");
+    hipError_t e = launch_group_dot(out, a, b, group_len, groups, (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "group_dot launch");
+}
+
+int fdk_relu_backward(float* dx, const float* dy, const float* y, size_t n, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return FDK_OK;
+    if (!dx || !dy || !y) return fail(FDK_ERR_INVALID_ARG, "NULL pointer");
+    hipError_t e = launch_relu_backward(dx, dy, y, n, (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "relu_backward launch");
+}
+
+int fdk_matvec(float* y, const float* A, const float* x, int rows, int cols, int transpose,
+               void* stream)
+{
+    g_err.clear();
+    if (rows < 1 || cols < 1) return fail(FDK_ERR_INVALID_ARG, "bad sizes");
+    if (!y || !A || !x) return fail(FDK_ERR_INVALID_ARG, "NULL pointer");
+    hipError_t e = launch_matvec(y, A, x, rows, cols, transpose, (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "matvec launch");
+}
+
+int fdk_adam(float* param, float* m, float* v, const float* grad, int n, float lr, float beta1,
+             float beta2, float eps, int step, void* stream)
+{
+    g_err.clear();
+    if (n < 0 || step < 1) return fail(FDK_ERR_INVALID_ARG, "n < 0 or step < 1");
+    if (n == 0) return FDK_OK;
+    if (!param || !m || !v || !grad) return fail(FDK_ERR_INVALID_ARG, "NULL pointer");
+    hipError_t e = launch_adam(param, m, v, grad, n, lr, beta1, beta2, eps, step,
+                               (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "adam launch");
+}
+
+int fdk_mse(float* grad, float* loss, const float* a, const float* b, size_t n, void* workspace,
+            size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return fail(FDK_ERR_INVALID_ARG, "n == 0");
+    if (!loss || !a || !b || !workspace) return fail(FDK_ERR_INVALID_ARG, "NULL pointer");
+    if (workspace_bytes < kMseParts * sizeof(double))
+        return fail(FDK_ERR_INVALID_ARG, "workspace too small");
+    hipError_t e = launch_mse(grad, loss, (double*)workspace, kMseParts, a, b, n,
+                              (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "mse launch");
+}
+
 int fdk_update_probe(float* a, size_t n, float s, void* stream)
 {
     g_err.clear();

@@ -90,6 +90,24 @@ struct PrefilterArgs {
     double scale;        // tau * dbeta
 };
 
+struct LearnConvArgs {
+    float* out;
+    const float* in;
+    const float* weight;
+    const float* bias;   // may be null
+    int rows, W, cin, cout, K, pad;
+    int relu, accumulate, transpose;
+};
+
+struct LearnGradArgs {
+    float* dweight;
+    float* dbias;        // may be null
+    const float* dout;
+    const float* in;
+    double* part;        // workspace: blocks x (cout*cin*K + cout)
+    int rows, W, cin, cout, K, pad;
+};
+
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s);
 hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, hipStream_t s);
@@ -100,6 +118,22 @@ hipError_t launch_zero(float* a, size_t n, hipStream_t st);
 hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s);
 hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s);
 hipError_t launch_prefilter(const PrefilterArgs& a, hipStream_t s);
+hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s);
+hipError_t launch_wgrad(const LearnGradArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_wgrad_long(const LearnGradArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_scale_groups(float* y, const float* x, const float* scale, size_t len,
+                               int groups, int accumulate, hipStream_t s);
+hipError_t launch_group_dot(float* out, const float* a, const float* b, size_t len, int groups,
+                            hipStream_t s);
+hipError_t launch_relu_backward(float* dx, const float* dy, const float* y, size_t n, hipStream_t s);
+hipError_t launch_matvec(float* y, const float* A, const float* x, int rows, int cols,
+                         int transpose, hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+hipError_t launch_mse(float* grad, float* loss, double* part, int nparts, const float* a,
+                      const float* b, size_t n, hipStream_t s);
+constexpr int kGradBlocks = 256;  // partial-sum blocks of the weight gradients
+constexpr int kMseParts = 1024;
 
 #ifndef FDK_FUSED_Z
 #define FDK_FUSED_Z 16

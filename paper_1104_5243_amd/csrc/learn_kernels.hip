@@ -1,0 +1,436 @@
+// Kernels of the learned Feldkamp filter (training and inference) for gfx950.
+//
+// The learned filter acts on detector rows: a long learned ramp (one
+// channel, K = 2W-1 taps), a per-view weight, and a small 1D CNN (9-tap
+// convolutions with 32 channels).  Everything is a batched row convolution
+//   out[r][co][j] = bias[co] + sum_{ci,t} w(co,ci,t) in[r][ci][j + t - pad]
+// (zero outside the row), its data gradient (the same convolution with the
+// transposed, flipped weights), its weight/bias gradient (a reduction over
+// rows and positions), plus elementwise helpers and Adam.
+//
+// conv_short_kernel: K <= 32, any channels.  A block covers 64 positions of
+//   one row for all output channels; the input tile (cin x (64 + K - 1)) is
+//   in LDS; wave w computes the output channels co = w, w + 4, ... so each
+//   weight is wave-uniform (scalar loads) and every LDS value feeds all of a
+//   wave's channels from registers.
+// conv_long_kernel: cin = cout = 1, long K (the ramp).  A block covers 256
+//   positions; FP64 accumulation (the ramp output is a small difference of
+//   large terms).
+// wgrad kernels: per-block partial sums over a strided set of rows, then a
+//   fixed-order reduction over the blocks (deterministic).
+#include "fdk_internal.h"
+
+namespace fdk {
+
+constexpr int kShortTile = 64;
+constexpr int kMaxShortK = 32;
+constexpr int kMaxCh = 64;
+
+__device__ __forceinline__ float conv_weight(const LearnConvArgs& a, int co, int ci, int t)
+{
+    // forward: weight[co][ci][t]; transposed: weight[ci][co][K-1-t] (stored
+    // with the roles of cin and cout swapped)
+    return a.transpose ? a.weight[((size_t)ci * a.cout + co) * a.K + (a.K - 1 - t)]
+                       : a.weight[((size_t)co * a.cin + ci) * a.K + t];
+}
+
+__global__ __launch_bounds__(256) void conv_short_kernel(LearnConvArgs a)
+{
+    extern __shared__ float tile[];  // cin x (kShortTile + K - 1)
+    const int row = blockIdx.y;
+    const int j0 = blockIdx.x * kShortTile;
+    const int span = kShortTile + a.K - 1;
+    const float* in = a.in + (size_t)row * a.cin * a.W;
+    for (int e = threadIdx.x; e < a.cin * span; e += 256) {
+        const int ci = e / span, s = e - ci * span;
+        const int j = j0 + s - a.pad;
+        tile[e] = (j >= 0 && j < a.W) ? in[(size_t)ci * a.W + j] : 0.0f;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = j0 + lane;
+    float* out = a.out + (size_t)row * a.cout * a.W;
+    // up to kMaxCh / 4 output channels per wave, in registers
+    float acc[kMaxCh / 4];
+    const int nco = (a.cout - wave + 3) / 4;  // channels co = wave + 4 q, q < nco
+#pragma unroll
+    for (int q = 0; q < kMaxCh / 4; ++q)
+        acc[q] = (q < nco && a.bias) ? a.bias[wave + 4 * q] : 0.0f;
+    for (int ci = 0; ci < a.cin; ++ci) {
+        const float* x = tile + ci * span + lane;
+        for (int t = 0; t < a.K; ++t) {
+            const float xv = x[t];
+#pragma unroll
+            for (int q = 0; q < kMaxCh / 4; ++q)
+                if (q < nco) acc[q] = fmaf(conv_weight(a, wave + 4 * q, ci, t), xv, acc[q]);
+        }
+    }
+    if (j < a.W) {
+#pragma unroll
+        for (int q = 0; q < kMaxCh / 4; ++q) {
+            if (q < nco) {
+                const int co = wave + 4 * q;
+                float v = acc[q];
+                float* o = out + (size_t)co * a.W + j;
+                if (a.accumulate) v += *o;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                *o = v;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void conv_long_kernel(LearnConvArgs a)
+{
+    extern __shared__ float tile[];  // 256 + K - 1
+    const int row = blockIdx.y;
+    const int j0 = blockIdx.x * 256;
+    const int span = 256 + a.K - 1;
+    const float* in = a.in + (size_t)row * a.W;
+    for (int s = threadIdx.x; s < span; s += 256) {
+        const int j = j0 + s - a.pad;
+        tile[s] = (j >= 0 && j < a.W) ? in[j] : 0.0f;
+    }
+    __syncthreads();
+    const int j = j0 + threadIdx.x;
+    if (j >= a.W) return;
+    double acc = a.bias ? (double)a.bias[0] : 0.0;
+    const float* x = tile + threadIdx.x;
+    for (int t = 0; t < a.K; ++t) acc = fma((double)conv_weight(a, 0, 0, t), (double)x[t], acc);
+    float* o = a.out + (size_t)row * a.W + j;
+    float v = (float)acc;
+    if (a.accumulate) v += *o;
+    if (a.relu) v = fmaxf(v, 0.0f);
+    *o = v;
+}
+
+hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s)
+{
+    if (a.K <= kMaxShortK) {
+        dim3 grid((a.W + kShortTile - 1) / kShortTile, a.rows);
+        const size_t lds = (size_t)a.cin * (kShortTile + a.K - 1) * sizeof(float);
+        hipLaunchKernelGGL(conv_short_kernel, grid, dim3(256), lds, s, a);
+    } else {
+        dim3 grid((a.W + 255) / 256, a.rows);
+        const size_t lds = (size_t)(256 + a.K - 1) * sizeof(float);
+        hipLaunchKernelGGL(conv_long_kernel, grid, dim3(256), lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// weight and bias gradients
+// ---------------------------------------------------------------------------
+// Block b sums over rows b, b + B, b + 2B, ... into
+//   part[b][(co*cin + ci)*K + t]  and  part_bias[b][co]
+// in FP64; thread e owns entries e, e + 256, ...  For each row the block
+// stages dout (cout x W) and in (cin x (W + K - 1), zero-padded) in LDS,
+// in chunks of kGradChunk positions.
+constexpr int kGradChunk = 128;
+
+__global__ __launch_bounds__(256) void wgrad_partial_kernel(LearnGradArgs a)
+{
+    extern __shared__ float lds[];
+    const int nw = a.cout * a.cin * a.K;
+    const int span = kGradChunk + a.K - 1;
+    float* dy = lds;                          // cout x kGradChunk
+    float* x = lds + a.cout * kGradChunk;     // cin x span
+    constexpr int kPer = 40;                  // entries per thread (<= 10240 total)
+    double acc[kPer];
+    double accb = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
+    for (int row = blockIdx.x; row < a.rows; row += gridDim.x) {
+        const float* drow = a.dout + (size_t)row * a.cout * a.W;
+        const float* xrow = a.in + (size_t)row * a.cin * a.W;
+        for (int j0 = 0; j0 < a.W; j0 += kGradChunk) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < a.cout * kGradChunk; e += 256) {
+                const int co = e / kGradChunk, s = e - co * kGradChunk;
+                const int j = j0 + s;
+                dy[e] = (j < a.W) ? drow[(size_t)co * a.W + j] : 0.0f;
+            }
+            for (int e = threadIdx.x; e < a.cin * span; e += 256) {
+                const int ci = e / span, s = e - ci * span;
+                const int j = j0 + s - a.pad;
+                x[e] = (j >= 0 && j < a.W) ? xrow[(size_t)ci * a.W + j] : 0.0f;
+            }
+            __syncthreads();
+            const int n = min(kGradChunk, a.W - j0);
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int e = threadIdx.x + 256 * q;
+                if (e < nw) {
+                    const int t = e % a.K;
+                    const int ci = (e / a.K) % a.cin;
+                    const int co = e / (a.K * a.cin);
+                    const float* d = dy + co * kGradChunk;
+                    const float* xx = x + ci * span + t;
+                    double s = 0.0;
+                    for (int p = 0; p < n; ++p) s = fma((double)d[p], (double)xx[p], s);
+                    acc[q] += s;
+                }
+            }
+            if (threadIdx.x < a.cout) {
+                const float* d = dy + threadIdx.x * kGradChunk;
+                double s = 0.0;
+                for (int p = 0; p < n; ++p) s += (double)d[p];
+                accb += s;
+            }
+        }
+    }
+    double* part = a.part + (size_t)blockIdx.x * (nw + a.cout);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < nw) part[e] = acc[q];
+    }
+    if (threadIdx.x < a.cout) part[nw + threadIdx.x] = accb;
+}
+
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(LearnGradArgs a, int nblocks)
+{
+    const int nw = a.cout * a.cin * a.K;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= nw + a.cout) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += a.part[(size_t)b * (nw + a.cout) + e];
+    if (e < nw)
+        a.dweight[e] = (float)s;
+    else if (a.dbias)
+        a.dbias[e - nw] = (float)s;
+}
+
+hipError_t launch_wgrad(const LearnGradArgs& a, int nblocks, hipStream_t s)
+{
+    const size_t lds =
+        (size_t)(a.cout * kGradChunk + a.cin * (kGradChunk + a.K - 1)) * sizeof(float);
+    hipLaunchKernelGGL(wgrad_partial_kernel, dim3(nblocks), dim3(256), lds, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = a.cout * a.cin * a.K + a.cout;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, nblocks);
+    return hipGetLastError();
+}
+
+// Long-kernel (cin = cout = 1) weight gradient: dweight[t] = sum_r sum_j
+// dout[r][j] in[r][j + t - pad].  Block b handles rows b, b + B, ...; each
+// thread owns taps t = threadIdx.x + 256 q.
+constexpr int kLongPer = 32;  // K <= 8192
+
+__global__ __launch_bounds__(256) void wgrad_long_partial_kernel(LearnGradArgs a)
+{
+    extern __shared__ float lds[];
+    float* dy = lds;          // W
+    float* x = lds + a.W;     // W + K - 1
+    double acc[kLongPer];
+    double accb = 0.0;
+#pragma unroll
+    for (int q = 0; q < kLongPer; ++q) acc[q] = 0.0;
+    const int span = a.W + a.K - 1;
+    for (int row = blockIdx.x; row < a.rows; row += gridDim.x) {
+        __syncthreads();
+        for (int s = threadIdx.x; s < a.W; s += 256) dy[s] = a.dout[(size_t)row * a.W + s];
+        for (int s = threadIdx.x; s < span; s += 256) {
+            const int j = s - a.pad;
+            x[s] = (j >= 0 && j < a.W) ? a.in[(size_t)row * a.W + j] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kLongPer; ++q) {
+            const int t = threadIdx.x + 256 * q;
+            if (t < a.K) {
+                double s = 0.0;
+                for (int p = 0; p < a.W; ++p) s = fma((double)dy[p], (double)x[p + t], s);
+                acc[q] += s;
+            }
+        }
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int p = 0; p < a.W; ++p) s += (double)dy[p];
+            accb += s;
+        }
+    }
+    double* part = a.part + (size_t)blockIdx.x * (a.K + 1);
+#pragma unroll
+    for (int q = 0; q < kLongPer; ++q) {
+        const int t = threadIdx.x + 256 * q;
+        if (t < a.K) part[t] = acc[q];
+    }
+    if (threadIdx.x == 0) part[a.K] = accb;
+}
+
+hipError_t launch_wgrad_long(const LearnGradArgs& a, int nblocks, hipStream_t s)
+{
+    const size_t lds = (size_t)(2 * a.W + a.K - 1) * sizeof(float);
+    hipLaunchKernelGGL(wgrad_long_partial_kernel, dim3(nblocks), dim3(256), lds, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int n = a.K + 1;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, nblocks);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise helpers
+// ---------------------------------------------------------------------------
+// y[g][i] = x[g][i] * scale[g] (+ y if accumulate)
+__global__ __launch_bounds__(256) void scale_groups_kernel(float* y, const float* x,
+                                                           const float* scale, size_t len,
+                                                           int groups, int accumulate)
+{
+    const size_t n = len * groups;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        float v = x[i] * scale[i / len];
+        if (accumulate) v += y[i];
+        y[i] = v;
+    }
+}
+
+// out[g] = sum_i a[g][i] * b[g][i] (FP64, one block per group)
+__global__ __launch_bounds__(256) void group_dot_kernel(float* out, const float* a, const float* b,
+                                                        size_t len)
+{
+    __shared__ double red[256];
+    const size_t base = (size_t)blockIdx.x * len;
+    double s = 0.0;
+    for (size_t i = threadIdx.x; i < len; i += 256) s += (double)a[base + i] * (double)b[base + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = (float)red[0];
+}
+
+// dx = dy where y > 0, else 0 (ReLU backward, y the ReLU output)
+__global__ __launch_bounds__(256) void relu_backward_kernel(float* dx, const float* dy,
+                                                            const float* y, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+        dx[i] = y[i] > 0.0f ? dy[i] : 0.0f;
+}
+
+// y = A x (A rows x cols, row-major) or y = A^T x; FP64 accumulation
+__global__ __launch_bounds__(256) void matvec_kernel(float* y, const float* A, const float* x,
+                                                     int rows, int cols, int transpose)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int n_out = transpose ? cols : rows;
+    if (i >= n_out) return;
+    double s = 0.0;
+    if (!transpose)
+        for (int c = 0; c < cols; ++c) s = fma((double)A[(size_t)i * cols + c], (double)x[c], s);
+    else
+        for (int r = 0; r < rows; ++r) s = fma((double)A[(size_t)r * cols + i], (double)x[r], s);
+    y[i] = (float)s;
+}
+
+// Adam (Kingma and Ba, 2015) with bias correction, step t >= 1
+__global__ __launch_bounds__(256) void adam_kernel(float* p, float* m, float* v, const float* g,
+                                                   int n, float lr, float b1, float b2, float eps,
+                                                   float c1, float c2)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// grad = 2 (a - b) / n, loss_part[block] = sum (a - b)^2 over the block's share
+__global__ __launch_bounds__(256) void mse_kernel(float* grad, double* part, const float* a,
+                                                  const float* b, size_t n)
+{
+    __shared__ double red[256];
+    const size_t stride = (size_t)gridDim.x * 256;
+    double s = 0.0;
+    const float inv = 2.0f / (float)n;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const float d = a[i] - b[i];
+        if (grad) grad[i] = d * inv;
+        s += (double)d * (double)d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_parts_kernel(float* out, const double* part, int n, double scale)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    out[0] = (float)(s * scale);
+}
+
+static unsigned blocks_for(size_t n)
+{
+    size_t b = (n + 255) / 256;
+    if (b > 256 * 64) b = 256 * 64;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_scale_groups(float* y, const float* x, const float* scale, size_t len,
+                               int groups, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(scale_groups_kernel, dim3(blocks_for(len * groups)), dim3(256), 0, s, y, x,
+                       scale, len, groups, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_dot(float* out, const float* a, const float* b, size_t len, int groups,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(group_dot_kernel, dim3(groups), dim3(256), 0, s, out, a, b, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_backward(float* dx, const float* dy, const float* y, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(relu_backward_kernel, dim3(blocks_for(n)), dim3(256), 0, s, dx, dy, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec(float* y, const float* A, const float* x, int rows, int cols,
+                         int transpose, hipStream_t s)
+{
+    const int n = transpose ? cols : rows;
+    hipLaunchKernelGGL(matvec_kernel, dim3((n + 255) / 256), dim3(256), 0, s, y, A, x, rows, cols,
+                       transpose);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, (float)step);
+    const float c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, m, v, g, n, lr, b1,
+                       b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse(float* grad, float* loss, double* part, int nparts, const float* a,
+                      const float* b, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(mse_kernel, dim3(nparts), dim3(256), 0, s, grad, part, a, b, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(64), 0, s, loss, part, nparts,
+                       1.0 / (double)n);
+    return hipGetLastError();
+}
+
+}  // namespace fdk
