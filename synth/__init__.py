@@ -307,23 +307,28 @@ def voxelize(ell: np.ndarray, N: int, voxel_size: float, origin, sub: int = 1,
     return out
 
 
-def voxelize_torch(ell: np.ndarray, N: int, voxel_size: float, origin, device):
-    """Point-sampled phantom density at the N^3 voxel centres, computed with
+def voxelize_torch(ell: np.ndarray, N: int, voxel_size: float, origin, device, sub: int = 1):
+    """Phantom density at the N^3 voxels, the mean of sub^3 regularly spaced
+    samples inside each voxel (sub = 1: the voxel centre), computed with
     torch on `device` (for generating many training volumes quickly)."""
     import torch
-    ax = [torch.tensor(origin[k], dtype=torch.float64, device=device) +
-          voxel_size * torch.arange(N, dtype=torch.float64, device=device) for k in range(3)]
-    z, y, x = torch.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
     vol = torch.zeros(N, N, N, dtype=torch.float64, device=device)
-    for E in np.asarray(ell, dtype=np.float64):
-        R = torch.tensor(E[6:15].reshape(3, 3), device=device)
-        d = [x - E[0], y - E[1], z - E[2]]
-        q = 0.0
-        for k in range(3):
-            t = (R[0, k] * d[0] + R[1, k] * d[1] + R[2, k] * d[2]) / E[3 + k]
-            q = q + t * t
-        vol += (q <= 1.0).to(torch.float64) * E[15]
-    return vol.float()
+    for sz in range(sub):
+        for sy in range(sub):
+            for sx in range(sub):
+                off = [(s_ + 0.5) / sub - 0.5 for s_ in (sx, sy, sz)]
+                ax = [origin[k] + voxel_size * (torch.arange(N, dtype=torch.float64, device=device)
+                                                + off[k]) for k in range(3)]
+                z, y, x = torch.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+                for E in np.asarray(ell, dtype=np.float64):
+                    R = torch.tensor(E[6:15].reshape(3, 3), device=device)
+                    d = [x - E[0], y - E[1], z - E[2]]
+                    q = 0.0
+                    for k in range(3):
+                        t = (R[0, k] * d[0] + R[1, k] * d[1] + R[2, k] * d[2]) / E[3 + k]
+                        q = q + t * t
+                    vol += (q <= 1.0).to(torch.float64) * E[15]
+    return (vol / (sub ** 3)).float()
 
 
 # --------------------------------------------------------------------------

@@ -198,3 +198,28 @@ def test_model_initialisation_is_plain_fbp(env):
     e = rel(y3.cpu().numpy(), q.cpu().numpy())
     print(f"learned filter at init vs plain pre-filter: rel {e:.2e}", flush=True)
     assert e <= 1e-4
+
+
+def test_learned_filter_beats_plain_fbp_on_held_out_phantoms(env):
+    """Train on 32 seeded phantoms (two passes, 62 views of 624x480, 128^3,
+    exact line integrals), then reconstruct two held-out phantoms: the
+    learned filter's masked RMSE must be below plain FBP's (the judge)."""
+    torch, fdk, GL, dev = env
+    g = synth.cone_beam_geometry(n_views=62, H=480, W=624, pixel=0.616)
+    geo = GL.geometry_from(g)
+    N = 128
+    vs, o = synth.volume_frame(N)
+    mask = torch.from_numpy(GL.fov_mask(N, vs, o, 110.0, 80.0)).to(dev)
+    model = GL.LearnedFilter(geo, dev)
+    model.sigma = GL.default_sigma(model, 1, N, vs, o)
+    model.sigma_t.fill_(1.0 / model.sigma)
+    model.sigma_f.fill_(model.sigma)
+    before = GL.evaluate(model, [9999, 9998], N, vs, o, mask)
+    for rp, rl in before:  # untrained: the learned path is plain FBP
+        assert rl == pytest.approx(rp, rel=1e-4)
+    GL.train(model, range(1, 33), N, vs, o, mask, epochs=2, lr=1e-3,
+             log=lambda m: print(m, flush=True))
+    after = GL.evaluate(model, [9999, 9998], N, vs, o, mask)
+    for rp, rl in after:
+        print(f"held-out RMSE: plain {rp:.4e} learned {rl:.4e}", flush=True)
+        assert rl < 0.98 * rp
