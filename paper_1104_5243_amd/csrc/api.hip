@@ -58,6 +58,12 @@ int initial_layout()
     return kPairs;
 }
 int g_layout = initial_layout();
+// forward projection through LDS tiles (FDK_FP_LDS=0 in the environment
+// selects direct global atomics)
+int g_fp_lds = []() {
+    const char* e = std::getenv("FDK_FP_LDS");
+    return (e && !std::strcmp(e, "0")) ? 0 : 1;
+}();
 constexpr size_t kMaxStagingBytes = size_t(4) << 30;
 
 // ---- kernel timing (per calling thread) ----------------------------------
@@ -351,7 +357,16 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
         const bool wcheck = fold_batch(A, P, nullptr, v0, cnt, N, voxel_size, origin, H, W);
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
-        e = launch_scatter(A, wcheck, stream);
+        if (wcheck || !g_fp_lds) {
+            e = launch_scatter(A, wcheck, stream);
+        } else {
+            FusedArgs B = A;  // 16 x 16 column tiles
+            B.tiles_x = (N + 15) / 16;
+            B.tiles_y = (N + 15) / 16;
+            const long long blocks = (long long)B.tiles_x * B.tiles_y * B.zchunks;
+            B.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+            e = launch_scatter_lds(B, stream);
+        }
         if (e != hipSuccess) return hip_fail(e, "forward projection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
         UnstageArgs U;
@@ -463,8 +478,8 @@ int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double
 {
     g_err.clear();
     if (n_views < 0) return fail(FDK_ERR_INVALID_ARG, "n_views=%d < 0", n_views);
-    if (H < 1 || W < 1 || W > 4000 || H > 32768)
-        return fail(FDK_ERR_INVALID_ARG, "detector %dx%d outside [1, 4000] x [1, 32768]", W, H);
+    if (H < 1 || W < 1 || W > 2000 || H > 32768)
+        return fail(FDK_ERR_INVALID_ARG, "detector %dx%d outside [1, 2000] x [1, 32768]", W, H);
     if (n_views == 0) return FDK_OK;
     if (!out || !in) return fail(FDK_ERR_INVALID_ARG, "out or in is NULL");
     if (out == in) return fail(FDK_ERR_INVALID_ARG, "out and in must be distinct buffers");

@@ -116,6 +116,8 @@ hipError_t launch_update_probe(float* a, size_t n, float s, hipStream_t st);
 hipError_t launch_zero(float* a, size_t n, hipStream_t st);
 // forward projection of a.vol into the padded planes at a.img (scatter)
 hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s);
+// as launch_scatter for w > 0 everywhere; tiles of 16 x 16 columns
+hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s);
 hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s);
 hipError_t launch_prefilter(const PrefilterArgs& a, hipStream_t s);
 hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s);

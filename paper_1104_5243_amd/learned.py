@@ -306,6 +306,7 @@ def train(model: LearnedFilter, seeds, N, voxel_size, origin, mask, epochs=1, lr
     import time
     gm = None
     step = 0
+    seeds = list(seeds)
     for ep in range(epochs):
         t0 = time.time()
         tot = 0.0
@@ -316,6 +317,9 @@ def train(model: LearnedFilter, seeds, N, voxel_size, origin, mask, epochs=1, lr
             model.apply_grads(grads, lr)
             tot += float(loss)
             step += 1
+            if step % 32 == 0:
+                log(f"  step {step}: mean loss so far this epoch {tot / (step - ep * len(seeds)):.4e}"
+                    f" ({time.time() - t0:.1f} s)")
         log(f"epoch {ep}: mean loss {tot / len(seeds):.4e} ({time.time() - t0:.1f} s, "
             f"{len(seeds)} steps)")
     return model
