@@ -37,7 +37,10 @@ PEAK_HBM_GBS = 8000.0
 # paper, Section 7.2: 3.79 GUP/s with IEEE divides, 512^3 x 496 views of
 # 1248x960, 2-socket Xeon X5670 (Westmere EP), all optimisations
 PAPER_GUPS = 3.79
-KERNEL_SRC = os.path.join(ROOT, "paper_1104_5243_amd", "csrc", "bp_kernels.hip")
+# the sources the fused kernel's launches depend on (kernel, argument
+# structs, device helpers, host set-up with its default layout)
+KERNEL_SRC = [os.path.join(ROOT, "paper_1104_5243_amd", "csrc", f)
+              for f in ("bp_kernels.hip", "gfx950_util.h", "fdk_internal.h", "api.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bp_fused_fdk512_traffic.txt")
 
 
@@ -46,9 +49,9 @@ def log(msg: str) -> None:
 
 
 def kernel_hash() -> str:
-    """Hash of the kernel source's code (comments and blank lines removed),
+    """Hash of the kernel sources' code (comments and blank lines removed),
     so that the recorded counter traffic stays tied to the code measured."""
-    text = open(KERNEL_SRC).read()
+    text = "".join(open(f).read() for f in KERNEL_SRC)
     text = re.sub(r"//[^\n]*", "", text)
     code = "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
     return hashlib.sha256(code.encode()).hexdigest()[:16]
@@ -71,6 +74,190 @@ def measured_traffic():
     return int(float(rec["hbm_bytes_per_launch"]))
 
 
+def _timed(torch, fdk, fn, warmup, steps):
+    """Wall time per step over `steps` calls (after `warmup`), and the mean
+    duration of the library's kernels inside, from its HIP events."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    fdk.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    kernel_ms, launches = fdk.profile_end()
+    return t, kernel_ms, launches
+
+
+def _common(args, metric, value, unit, t, dtype, workload, roofline, cpu):
+    return {
+        "metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": workload}, "roofline": roofline, "cpu_baseline": cpu,
+    }
+
+
+def bench_forward(args, torch, fdk, synth, dev):
+    """Matched forward projection of a 256^3 phantom volume onto 248 views of
+    624x480 (the exact transpose of the backprojection)."""
+    import oracle
+    geom, ell, vs, origin, N = synth.workload("fdk256x8")
+    V, H, W = geom.n_views, geom.H, geom.W
+    vol = synth.voxelize_torch(ell, N, vs, origin, dev, sub=1)
+    proj = torch.zeros(V, H, W, device=dev)
+
+    def step():
+        proj.zero_()
+        fdk.forward_project(proj, vol, geom.P, vs, origin)
+
+    t, kms, launches = _timed(torch, fdk, step, args.warmup, args.steps)
+    updates = float(N) ** 3 * V
+    ks = kms / 1e3
+    ach = FLOP_PER_UPDATE * updates * args.steps / ks / 1e12
+    log(f"forward: {t * 1e3:.2f} ms/step, {updates / t / 1e9:.1f} GUP/s; "
+        f"{launches} scatter launches, {kms / max(launches, 1):.3f} ms each")
+    # oracle on a bounded sample: the same volume, the first Vs views
+    Vs = 16
+    vol_h = vol.double().cpu().numpy()
+    t0 = time.perf_counter()
+    ref = oracle.forward_project(vol_h, geom.P[:Vs], H, W, vs, origin)
+    tc = time.perf_counter() - t0
+    step()
+    torch.cuda.synchronize()
+    err = oracle.rel_rmse(proj[:Vs].double().cpu().numpy(), ref)
+    out = _common(
+        args, "forward projection voxel-view pairs/s at 256^3 x 248 views of 624x480",
+        round(updates / t / 1e9, 2), "GUP/s", t, "f32",
+        f"fdk256x8 forward: {N}^3 FP32 phantom volume, {V} views of {W}x{H}",
+        {"bound": "alu", "achieved": round(ach, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
+         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+         "kernel": "fp_lds_kernel", "launches_per_step": launches // args.steps,
+         "kernel_ms_per_step": round(kms / args.steps, 3)},
+        {"value": round(float(N) ** 3 * Vs / tc / 1e9, 4), "unit": "GUP/s",
+         "cores": oracle.threads(), "kind": "oracle",
+         "sample": f"the {N}^3 volume onto the first {Vs} of {V} views, FP64, {tc:.1f} s"})
+    out["rel_rmse_vs_oracle"] = float(f"{err:.3e}")
+    return out
+
+
+def bench_prefilter(args, torch, fdk, synth, dev):
+    """Feldkamp pre-filter (cosine x Parker x Ram-Lak, FP64 inside) of the
+    496 line-integral views of 1248x960."""
+    import math
+
+    import numpy as np
+
+    from oracle.prefilter import fdk_prefilter
+    geom, ell, vs, origin, N = synth.workload("fdk512")
+    V, H, W = geom.n_views, geom.H, geom.W
+    t0 = time.time()
+    li = synth.line_integrals(geom, ell)
+    log(f"line integrals {V}x{H}x{W} in {time.time() - t0:.1f}s")
+    li_d = torch.from_numpy(li).to(dev)
+    out_d = torch.empty_like(li_d)
+    delta = 0.5 * (geom.arc - math.pi)
+
+    def step():
+        fdk.prefilter(out_d, li_d, float(geom.betas[0]), geom.dbeta, delta, geom.sid, geom.sdd,
+                      geom.pixel)
+
+    t, kms, launches = _timed(torch, fdk, step, args.warmup, args.steps)
+    rows = V * H
+    # per output: the centre tap and (W/2 odd taps) x (one add + one FMA)
+    flop = rows * W * (1 + 3 * (W // 2))
+    ks = kms / 1e3
+    ach = flop * args.steps / ks / 1e12
+    log(f"prefilter: {t * 1e3:.2f} ms/step, {ach:.2f} TFLOP/s FP64")
+    Vs = 2
+    t0 = time.perf_counter()
+    ref = fdk_prefilter(li[:Vs], geom.betas[:Vs], delta, geom.dbeta, geom.sid, geom.sdd,
+                        geom.pixel)
+    tc = time.perf_counter() - t0
+    err = float(np.sqrt(((out_d[:Vs].double().cpu().numpy() - ref) ** 2).sum()
+                        / (ref ** 2).sum()))
+    out = _common(
+        args, "pre-filtered detector rows/s, 496 views of 1248x960", round(rows / t / 1e6, 3),
+        "Mrow/s", t, "f64",
+        f"fdk512 pre-filter: {V} line-integral views of {W}x{H}, FP32 in/out, FP64 inside",
+        {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
+         "frac": round(ach / 78.6, 4), "traffic": None, "kernel": "prefilter_kernel",
+         "launches_per_step": launches // args.steps,
+         "kernel_ms_per_step": round(kms / args.steps, 3)},
+        {"value": round(Vs * H / tc / 1e6, 5), "unit": "Mrow/s", "cores": 1, "kind": "oracle",
+         "sample": f"the first {Vs} of {V} views ({Vs * H} rows), np.convolve in FP64, "
+                   f"{tc:.1f} s"})
+    out["rel_rmse_vs_oracle"] = float(f"{err:.3e}")
+    return out
+
+
+def bench_learn_step(args, torch, fdk, synth, dev):
+    """One training step of the learned filter (forward through the filter
+    and the backprojection, masked MSE, backward through the forward
+    projector, the CNN, the view weights and the ramp, Adam) at 128^3 x 62
+    views of 624x480; the phantom's data are resident before timing."""
+    import oracle
+    from oracle import learned as OL
+    from paper_1104_5243_amd import learned as GL
+    g = synth.cone_beam_geometry(n_views=62, H=480, W=624, pixel=0.616)
+    geo = GL.geometry_from(g)
+    N = 128
+    vs, o = synth.volume_frame(N)
+    mask = torch.from_numpy(GL.fov_mask(N, vs, o, 110.0, 80.0)).to(dev)
+    model = GL.LearnedFilter(geo, dev)
+    model.sigma = GL.default_sigma(model, 1, N, vs, o)
+    model.sigma_t.fill_(1.0 / model.sigma)
+    model.sigma_f.fill_(model.sigma)
+    gt, p = GL.phantom_case(1, geo, N, vs, o, dev)
+    gm = gt * mask
+
+    def step():
+        _, grads = model.loss_and_grads(p, gm, mask, N, vs, o)
+        model.apply_grads(grads, 0.0)  # lr 0: every kernel runs, parameters stay
+
+    t, kms, launches = _timed(torch, fdk, step, args.warmup, args.steps)
+    # the dominant kernel: the 32 -> 32 channel, 9-tap row convolution
+    R, W = geo.V * geo.H, geo.W
+    a1 = torch.randn(R, GL.CH, W, device=dev)
+    a2 = torch.empty_like(a1)
+
+    def conv():
+        fdk.conv_rows(a2, a1, model.W2, model.b2, R, W, GL.CH, GL.CH, GL.KC, GL.KC // 2,
+                      fdk.CONV_RELU)
+
+    tcv, cms, cl = _timed(torch, fdk, conv, 1, 5)
+    conv_s = cms / cl / 1e3
+    conv_flop = 2.0 * R * W * GL.CH * GL.CH * GL.KC
+    ach = conv_flop / conv_s / 1e12
+    log(f"learn step: {t * 1e3:.1f} ms; conv 32->32: {conv_s * 1e3:.3f} ms, {ach:.1f} TFLOP/s")
+    # oracle step on a bounded sample: 2 of the 62 views
+    Vs = 2
+    params = {n: getattr(model, n).double().cpu().numpy() for n in model.params}
+    params["lam"] = params["lam"][:Vs]
+    T = GL.weight_table(geo)[:Vs]
+    M, _, _ = GL.ramp_basis(geo)
+    t0 = time.perf_counter()
+    OL.loss_and_grads(params, p[:Vs].double().cpu().numpy(), T, M, geo.P[:Vs], N, vs, o,
+                      model.sigma, gt.double().cpu().numpy(), mask.double().cpu().numpy())
+    tc = time.perf_counter() - t0
+    out = _common(
+        args, "learned-filter training steps/s at 128^3 x 62 views of 624x480",
+        round(1.0 / t, 3), "steps/s", t, "f32",
+        "learn128: one Adam step of the learned Feldkamp filter (1025-bin ramp, 62 view "
+        "weights, 1->32->32->1 9-tap row CNN) through backprojection and its adjoint",
+        {"bound": "alu", "achieved": round(ach, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
+         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+         "kernel": "conv_short_kernel (32->32, K=9)",
+         "kernel_ms": round(conv_s * 1e3, 3)},
+        {"value": round(Vs / geo.V / tc, 5), "unit": "steps/s", "cores": oracle.threads(),
+         "kind": "oracle",
+         "sample": f"FP64 oracle step on {Vs} of {geo.V} views ({tc:.1f} s), scaled by "
+                   f"{Vs}/{geo.V} to a full step"})
+    out["library_kernel_ms_per_step"] = round(kms / args.steps, 3)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +274,11 @@ def main() -> int:
                     help="z slices of the 512^3 volume in the CPU-baseline sample")
     ap.add_argument("--probe-hbm", action="store_true",
                     help="also run the update benchmark a[i] = s*a[i] over 2 GiB")
+    ap.add_argument("--path", choices=("backproject", "forward", "prefilter", "learn-step"),
+                    default="backproject",
+                    help="which part to measure: the backprojection (default), the matched "
+                         "forward projector, the Feldkamp pre-filter, or one training step "
+                         "of the learned filter")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -107,6 +299,11 @@ def main() -> int:
     fdk.lib()  # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.path != "backproject":
+        out = {"forward": bench_forward, "prefilter": bench_prefilter,
+               "learn-step": bench_learn_step}[args.path](args, torch, fdk, synth, dev)
+        print(json.dumps(out), flush=True)
+        return 0
 
     geom, ell, vs, origin, N = synth.workload(args.workload)
     V, H, W = geom.n_views, geom.H, geom.W

@@ -216,10 +216,11 @@ int fdk_mse(float* grad, float* loss, const float* a, const float* b, size_t n, 
 int fdk_update_probe(float* a, size_t n, float s, void* stream);
 
 /*
- * Timing of the backprojection kernels themselves.  After
- * fdk_profile_begin(), every backprojection kernel launch is bracketed by
- * HIP events on its stream; fdk_profile_end() waits for them and returns
- * the summed kernel milliseconds and the launch count, then stops timing.
+ * Timing of the library's main kernels themselves.  After
+ * fdk_profile_begin(), every launch of the backprojection, forward
+ * projection, pre-filter and row-convolution kernels is bracketed by HIP
+ * events on its stream; fdk_profile_end() waits for them and returns the
+ * summed kernel milliseconds and the launch count, then stops timing.
  * Per thread of the caller; not for use across threads.
  */
 int fdk_profile_begin(void);
@@ -227,6 +228,28 @@ int fdk_profile_end(double* kernel_ms, int* launches);
 
 /* Views per backprojection launch (1..64, default 64); 0 reads it back. */
 int fdk_set_batch(int views_per_pass);
+
+/*
+ * Staged-plane layout of the fused backprojection (a tuning knob; every
+ * layout computes the same interpolation, Section 3.2 part 3, and results
+ * differ only by rounding).  Element (r, c) of a zero-padded staged plane
+ * holds, with p(r, c) the padded view's pixel:
+ *   FDK_LAYOUT_ROWS   p(r, c)                                (two loads per sample)
+ *   FDK_LAYOUT_PAIRS  p(r, c), p(r+1, c)                     (one load)
+ *   FDK_LAYOUT_QUADS  p(r, c), p(r, c+1), p(r+1, c), p(r+1, c+1)
+ *   FDK_LAYOUT_DPAIRS p(r, c), p(r+1, c) - p(r, c)
+ *   FDK_LAYOUT_DQUADS p00, p10 - p00, p01 - p00, (p11 - p01) - (p10 - p00)
+ * (differences rounded to the storage type).  Applies to calls made after
+ * it (default FDK_LAYOUT_DPAIRS); -1 reads the current layout back.  Returns the layout or a negative
+ * error code (FDK_ERR_INVALID_ARG for an unknown layout).  The environment
+ * variable FDK_LAYOUT=rows|pairs|quads|dpairs|dquads sets the initial value.
+ */
+#define FDK_LAYOUT_ROWS 0
+#define FDK_LAYOUT_PAIRS 1
+#define FDK_LAYOUT_QUADS 2
+#define FDK_LAYOUT_DPAIRS 3
+#define FDK_LAYOUT_DQUADS 4
+int fdk_set_layout(int layout);
 
 /* Frees the library's staging buffers (waits for their last users). */
 int fdk_release(void);

@@ -32,7 +32,7 @@ EXPORTS = (
     "fdk_prefilter", "fdk_conv_rows", "fdk_conv_rows_wgrad_workspace", "fdk_conv_rows_wgrad",
     "fdk_scale_groups", "fdk_group_dot", "fdk_relu_backward", "fdk_matvec", "fdk_adam", "fdk_mse",
     "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
-    "fdk_release", "fdk_last_error", "fdk_version",
+    "fdk_set_layout", "fdk_release", "fdk_last_error", "fdk_version",
 )
 
 _lib = None
@@ -376,6 +376,17 @@ def profile_end():
 
 def set_batch(views_per_pass: int) -> int:
     return _check(lib().fdk_set_batch(int(views_per_pass)))
+
+
+LAYOUTS = {"rows": 0, "pairs": 1, "quads": 2, "dpairs": 3, "dquads": 4}
+
+
+def set_layout(layout) -> str:
+    """Staged-plane layout of the fused backprojection (a name of LAYOUTS, or
+    None to read it back); returns the layout in effect."""
+    code = -1 if layout is None else LAYOUTS[layout]
+    got = _check(lib().fdk_set_layout(code))
+    return next(k for k, v in LAYOUTS.items() if v == got)
 
 
 def release():

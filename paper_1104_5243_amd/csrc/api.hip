@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -45,19 +46,22 @@ struct Staging {
 };
 std::mutex g_stage_mu;
 std::unordered_map<int, Staging> g_stage;
-int g_batch = kMaxBatch;
+std::atomic<int> g_batch{kMaxBatch};
 
-// Staged layout of the fused path (tuning knob; FDK_LAYOUT=rows|pairs|quads
-// in the environment overrides the default at load time).
+// Staged layout of the fused path (tuning knob; FDK_LAYOUT=rows|pairs|quads|
+// dpairs|dquads in the environment overrides the default at load time).
 int initial_layout()
 {
     const char* e = std::getenv("FDK_LAYOUT");
     if (e && !std::strcmp(e, "rows")) return kRows;
     if (e && !std::strcmp(e, "pairs")) return kPairs;
     if (e && !std::strcmp(e, "quads")) return kQuads;
-    return kPairs;
+    if (e && !std::strcmp(e, "dpairs")) return kDPairs;
+    if (e && !std::strcmp(e, "dquads")) return kDQuads;
+    return kDPairs;
 }
-int g_layout = initial_layout();
+std::atomic<int> g_layout{initial_layout()};
+
 // forward projection through LDS tiles (FDK_FP_LDS=0 in the environment
 // selects direct global atomics)
 int g_fp_lds = []() {
@@ -285,7 +289,7 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
     const size_t esz = storage_size(dtype);
     const int layout = g_layout;
-    const size_t elem = esz * (layout == kRows ? 1 : layout == kPairs ? 2 : 4);
+    const size_t elem = esz * layout_width(layout);
     const size_t plane_bytes = (size_t)Hp * Wp * elem;
     if (plane_bytes >= (size_t(1) << 31))
         return fail(FDK_ERR_UNSUPPORTED, "staged view of %zu bytes exceeds 2 GiB", plane_bytes);
@@ -397,7 +401,7 @@ int run_plain(float* volume, int N, float voxel_size, const float* origin, const
     A.oy = origin[1];
     A.oz = origin[2];
     A.vs = voxel_size;
-    const int batch = std::min(g_batch, n_views);
+    const int batch = std::min(g_batch.load(), n_views);
     for (int v0 = 0; v0 < n_views; v0 += batch) {
         const int cnt = std::min(batch, n_views - v0);
         A.proj = proj + (size_t)v0 * H * W;
@@ -503,8 +507,12 @@ int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double
     A.pixel = pixel;
     A.tau = pixel * sid / sdd;
     A.scale = pixel * sid / sdd * dbeta;
+    hipEvent_t t0;
+    int rc = timed_begin((hipStream_t)stream, &t0);
+    if (rc != FDK_OK) return rc;
     hipError_t e = launch_prefilter(A, (hipStream_t)stream);
-    return e == hipSuccess ? FDK_OK : hip_fail(e, "prefilter launch");
+    if (e != hipSuccess) return hip_fail(e, "prefilter launch");
+    return timed_end((hipStream_t)stream, t0);
 }
 
 int fdk_conv_rows(float* out, const float* in, const float* weight, const float* bias, int rows,
@@ -539,8 +547,12 @@ int fdk_conv_rows(float* out, const float* in, const float* weight, const float*
     A.relu = (flags & FDK_CONV_RELU) ? 1 : 0;
     A.accumulate = (flags & FDK_CONV_ACCUMULATE) ? 1 : 0;
     A.transpose = (flags & FDK_CONV_TRANSPOSE) ? 1 : 0;
+    hipEvent_t t0;
+    int rc = timed_begin((hipStream_t)stream, &t0);
+    if (rc != FDK_OK) return rc;
     hipError_t e = launch_conv(A, (hipStream_t)stream);
-    return e == hipSuccess ? FDK_OK : hip_fail(e, "conv launch");
+    if (e != hipSuccess) return hip_fail(e, "conv launch");
+    return timed_end((hipStream_t)stream, t0);
 }
 
 size_t fdk_conv_rows_wgrad_workspace(int cin, int cout, int K)
@@ -704,6 +716,16 @@ int fdk_set_batch(int views_per_pass)
                     kMaxBatch);
     g_batch = views_per_pass;
     return g_batch;
+}
+
+int fdk_set_layout(int layout)
+{
+    g_err.clear();
+    if (layout == -1) return g_layout;
+    if (layout < kRows || layout > kDQuads)
+        return fail(FDK_ERR_INVALID_ARG, "layout=%d is not one of 0..4", layout);
+    g_layout = layout;
+    return g_layout;
 }
 
 int fdk_release(void)

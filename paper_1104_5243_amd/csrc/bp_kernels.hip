@@ -9,9 +9,12 @@
 //     part 1: (u'w, v'w, w) by three FMAs from a per-column base, one
 //             reciprocal r = 1/w, u' = u'w r, v' = v'w r;
 //     part 2: floor / fraction, clamp into the staged plane's zero border,
-//             two 2-element loads (the horizontally adjacent tap pairs the
-//             paper loads pairwise, Section 4.1);
-//     part 3: bilinear interpolation and acc += r^2 * fx.
+//             one 16-byte load of two adjacent staged elements (the
+//             horizontally adjacent tap pairs the paper loads pairwise,
+//             Section 4.1, each element holding a vertical tap pair);
+//     part 3: bilinear interpolation and acc += r^2 * fx; with the default
+//             staged layout the elements hold (p, p_below - p), so the
+//             interpolation takes 4 instructions instead of 6.
 //   The projections are read from zero-padded staged planes (Section 3.3),
 //   so no tap needs a bounds test: out-of-detector taps are clamped onto
 //   the zero border.
@@ -20,6 +23,7 @@
 // stage: copies a batch of views into zero-padded planes.
 // update probe: a[i] = s * a[i], the paper's bandwidth benchmark.
 #include "fdk_internal.h"
+#include "gfx950_util.h"
 
 namespace fdk {
 
@@ -29,22 +33,6 @@ namespace fdk {
 struct TF32 { using elem = float; };
 struct TF16 { using elem = uint16_t; };
 struct TBF16 { using elem = uint16_t; };
-
-// floor(x) as an integer in one instruction (x is finite and clamped).
-__device__ __forceinline__ int cvt_floor(float x)
-{
-    int r;
-    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
-// a * b + c on 24-bit signed a, b (|a|, |b| < 2^23) in one instruction.
-__device__ __forceinline__ int mad_i24(int a, int b, int c)
-{
-    int r;
-    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
 
 // ---------------------------------------------------------------------------
 // stage
@@ -56,9 +44,39 @@ __device__ __forceinline__ E staged_pixel(const StageArgs& a, const E* src, int 
     return (j >= 0 && j < a.W && k >= 0 && k < a.H) ? src[(size_t)k * a.W + j] : E(0);
 }
 
-template <typename E, int LAYOUT>
+// storage element <-> float; float -> storage rounds to nearest even
+__device__ __forceinline__ float to_f(TF32, float x) { return x; }
+__device__ __forceinline__ float to_f(TF16, uint16_t x) { return (float)__builtin_bit_cast(_Float16, x); }
+__device__ __forceinline__ float to_f(TBF16, uint16_t x)
+{
+    return __builtin_bit_cast(float, (uint32_t)x << 16);
+}
+__device__ __forceinline__ float from_f(TF32, float d) { return d; }
+__device__ __forceinline__ uint16_t from_f(TF16, float d)
+{
+    return __builtin_bit_cast(uint16_t, (_Float16)d);
+}
+__device__ __forceinline__ uint16_t from_f(TBF16, float d)
+{
+    const uint32_t u = __builtin_bit_cast(uint32_t, d);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+// b - a, and (d - c) - (b - a), rounded to the storage type
+template <typename TT, typename E>
+__device__ __forceinline__ E diff_elem(TT t, E b, E a)
+{
+    return from_f(t, to_f(t, b) - to_f(t, a));
+}
+template <typename TT, typename E>
+__device__ __forceinline__ E diff2_elem(TT t, E d, E c, E b, E a)
+{
+    return from_f(t, (to_f(t, d) - to_f(t, c)) - (to_f(t, b) - to_f(t, a)));
+}
+
+template <typename TT, int LAYOUT>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs a)
 {
+    using E = typename TT::elem;
     const int col = blockIdx.x * 256 + threadIdx.x;
     const int row = blockIdx.y;
     const int view = blockIdx.z;
@@ -71,6 +89,17 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a)
     } else if (LAYOUT == kPairs) {
         E v[2] = {staged_pixel(a, src, row, col), staged_pixel(a, src, row + 1, col)};
         __builtin_memcpy(dst + 2 * e, v, sizeof(v));
+    } else if (LAYOUT == kDPairs) {
+        const E p0 = staged_pixel(a, src, row, col), p1 = staged_pixel(a, src, row + 1, col);
+        E v[2] = {p0, diff_elem(TT{}, p1, p0)};
+        __builtin_memcpy(dst + 2 * e, v, sizeof(v));
+    } else if (LAYOUT == kDQuads) {
+        const E p00 = staged_pixel(a, src, row, col), p01 = staged_pixel(a, src, row, col + 1);
+        const E p10 = staged_pixel(a, src, row + 1, col);
+        const E p11 = staged_pixel(a, src, row + 1, col + 1);
+        E v[4] = {p00, diff_elem(TT{}, p10, p00), diff_elem(TT{}, p01, p00),
+                  diff2_elem(TT{}, p11, p01, p10, p00)};
+        __builtin_memcpy(dst + 4 * e, v, sizeof(v));
     } else {
         E v[4] = {staged_pixel(a, src, row, col), staged_pixel(a, src, row, col + 1),
                   staged_pixel(a, src, row + 1, col), staged_pixel(a, src, row + 1, col + 1)};
@@ -78,39 +107,36 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a)
     }
 }
 
+template <typename TT>
+static void launch_stage_t(const StageArgs& a, dim3 grid, hipStream_t s)
+{
+    if (a.layout == kRows)
+        hipLaunchKernelGGL((stage_kernel<TT, kRows>), grid, dim3(256), 0, s, a);
+    else if (a.layout == kPairs)
+        hipLaunchKernelGGL((stage_kernel<TT, kPairs>), grid, dim3(256), 0, s, a);
+    else if (a.layout == kDPairs)
+        hipLaunchKernelGGL((stage_kernel<TT, kDPairs>), grid, dim3(256), 0, s, a);
+    else if (a.layout == kDQuads)
+        hipLaunchKernelGGL((stage_kernel<TT, kDQuads>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((stage_kernel<TT, kQuads>), grid, dim3(256), 0, s, a);
+}
+
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s)
 {
     dim3 grid((a.Wp + 255) / 256, a.Hp, a.count);
-#define FDK_STAGE(E)                                                                     \
-    do {                                                                                 \
-        if (a.layout == kRows)                                                           \
-            hipLaunchKernelGGL((stage_kernel<E, kRows>), grid, dim3(256), 0, s, a);      \
-        else if (a.layout == kPairs)                                                     \
-            hipLaunchKernelGGL((stage_kernel<E, kPairs>), grid, dim3(256), 0, s, a);     \
-        else                                                                             \
-            hipLaunchKernelGGL((stage_kernel<E, kQuads>), grid, dim3(256), 0, s, a);     \
-    } while (0)
     if (storage == kF32)
-        FDK_STAGE(float);
+        launch_stage_t<TF32>(a, grid, s);
+    else if (storage == kF16)
+        launch_stage_t<TF16>(a, grid, s);
     else
-        FDK_STAGE(uint16_t);
-#undef FDK_STAGE
+        launch_stage_t<TBF16>(a, grid, s);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // fused
 // ---------------------------------------------------------------------------
-// Raw buffer loads: a 32-bit byte offset per lane, the plane base in a
-// buffer descriptor, and the second tap row reached through the scalar
-// offset.  An offset outside the descriptor's range would read 0 instead of
-// faulting; the clamps keep every offset inside the staged plane.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
-                                             0x00020000);
-}
-
 // The four taps (tl, tr, bl, br) of element (iv, iu): `off` is the byte
 // offset of that element, `row` the byte stride of a plane row.  (The
 // buffer-load builtins' vector results are reinterpreted whole; extracting
@@ -125,10 +151,11 @@ __device__ __forceinline__ void load_taps(TF32, __amdgpu_buffer_rsrc_t r, uint32
         const float2 t = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
         const float2 b = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, row, 0));
         tl = t.x; tr = t.y; bl = b.x; br = b.y;
-    } else if (LAYOUT == kPairs) {  // (tl, bl, tr, br)
+    } else if (LAYOUT == kPairs || LAYOUT == kDPairs) {  // (tl, bl, tr, br); dpairs: bl, br
+        // hold the differences bl - tl, br - tr
         const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
         tl = q.x; bl = q.y; tr = q.z; br = q.w;
-    } else {  // (tl, tr, bl, br)
+    } else {  // quads: (tl, tr, bl, br); dquads: (p00, dv, dh, dd) in that order
         const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
         tl = q.x; tr = q.y; bl = q.z; br = q.w;
     }
@@ -137,7 +164,9 @@ __device__ __forceinline__ void load_taps(TF32, __amdgpu_buffer_rsrc_t r, uint32
 // 16-bit storage: the two dwords holding the four taps, as loaded.
 //   rows : w0 = (tl, tr), w1 = (bl, br)   [low half first]
 //   pairs: w0 = (tl, bl), w1 = (tr, br)
+//   dpairs: w0 = (tl, bl - tl), w1 = (tr, br - tr)
 //   quads: w0 = (tl, tr), w1 = (bl, br)
+//   dquads: w0 = (p00, dv), w1 = (dh, dd)
 template <int LAYOUT>
 __device__ __forceinline__ uint2 load_taps16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t row)
 {
@@ -175,6 +204,14 @@ __device__ __forceinline__ float lerp16(float a, float left, float right)
 template <int LAYOUT>
 __device__ __forceinline__ float bilerp16(TF16, uint2 q, float au, float av)
 {
+    if (LAYOUT == kDPairs) {
+        // columns first: left/right = t + av * d with FP16 operands
+        const float left = fmaf(av, h_hi(q.x), h_lo(q.x));
+        const float right = fmaf(av, h_hi(q.y), h_lo(q.y));
+        return fmaf(au, right - left, left);
+    }
+    if (LAYOUT == kDQuads)
+        return fmaf(au, fmaf(av, h_hi(q.y), h_lo(q.y)), fmaf(av, h_hi(q.x), h_lo(q.x)));
     float top, bot;
     if (LAYOUT == kPairs) {
         top = lerp16(au, h_lo(q.x), h_lo(q.y));
@@ -189,6 +226,13 @@ __device__ __forceinline__ float bilerp16(TF16, uint2 q, float au, float av)
 template <int LAYOUT>
 __device__ __forceinline__ float bilerp16(TBF16, uint2 q, float au, float av)
 {
+    if (LAYOUT == kDPairs) {
+        const float left = fmaf(av, b_hi(q.x), b_lo(q.x));
+        const float right = fmaf(av, b_hi(q.y), b_lo(q.y));
+        return fmaf(au, right - left, left);
+    }
+    if (LAYOUT == kDQuads)
+        return fmaf(au, fmaf(av, b_hi(q.y), b_lo(q.y)), fmaf(av, b_hi(q.x), b_lo(q.x)));
     float tl, tr, bl, br;
     if (LAYOUT == kPairs) {
         tl = b_lo(q.x); bl = b_hi(q.x); tr = b_lo(q.y); br = b_hi(q.y);
@@ -218,7 +262,7 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const float*
 {
     using E = typename TT::elem;
     constexpr bool kIsF32 = sizeof(E) == 4;
-    constexpr uint32_t kElem = sizeof(E) * (LAYOUT == kRows ? 1 : LAYOUT == kPairs ? 2 : 4);
+    constexpr uint32_t kElem = sizeof(E) * layout_width(LAYOUT);
     const int Wp = A.Wp;
     const uint32_t row_bytes = (uint32_t)Wp * kElem;
     const uint32_t centre_bytes = (uint32_t)A.origin_off * kElem;
@@ -257,7 +301,15 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const float*
         for (int q = 0; q < kGroup; ++q) {
             // part 3
             float fx;
-            if constexpr (kIsF32) {
+            if constexpr (kIsF32 && LAYOUT == kDQuads) {
+                // (tl, tr, bl, br) hold (p00, dv, dh, dd)
+                fx = fmaf(au[q], fmaf(av[q], br[q], bl[q]), fmaf(av[q], tr[q], tl[q]));
+            } else if constexpr (kIsF32 && LAYOUT == kDPairs) {
+                // bl, br hold the vertical differences
+                const float left = fmaf(av[q], bl[q], tl[q]);
+                const float right = fmaf(av[q], br[q], tr[q]);
+                fx = fmaf(au[q], right - left, left);
+            } else if constexpr (kIsF32) {
                 const float top = fmaf(au[q], tr[q] - tl[q], tl[q]);
                 const float bot = fmaf(au[q], br[q] - bl[q], bl[q]);
                 fx = fmaf(av[q], bot - top, top);
@@ -277,7 +329,7 @@ template <typename TT, int LAYOUT, bool WCHECK>
 __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused_kernel(const FusedArgs A)
 {
     using E = typename TT::elem;
-    constexpr uint32_t kElem = sizeof(E) * (LAYOUT == kRows ? 1 : LAYOUT == kPairs ? 2 : 4);
+    constexpr uint32_t kElem = sizeof(E) * layout_width(LAYOUT);
     int bid = blockIdx.x;
     if (A.xcd_remap) {
         const int per = gridDim.x >> 3;
@@ -365,6 +417,10 @@ static void launch_fused_l(const FusedArgs& a, int layout, bool wcheck, hipStrea
         launch_fused_t<TT, kRows>(a, wcheck, s);
     else if (layout == kPairs)
         launch_fused_t<TT, kPairs>(a, wcheck, s);
+    else if (layout == kDPairs)
+        launch_fused_t<TT, kDPairs>(a, wcheck, s);
+    else if (layout == kDQuads)
+        launch_fused_t<TT, kDQuads>(a, wcheck, s);
     else
         launch_fused_t<TT, kQuads>(a, wcheck, s);
 }
@@ -377,292 +433,6 @@ hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck
         launch_fused_l<TF16>(a, layout, wcheck, s);
     else
         launch_fused_l<TBF16>(a, layout, wcheck, s);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// forward projection: the exact transpose of the backprojection
-// ---------------------------------------------------------------------------
-// Every voxel value times r^2 = 1/w^2 is spread onto the four taps the
-// backprojection reads, with the same bilinear weights (1-au)(1-av), au(1-av),
-// (1-au)av, au av.  The targets are padded FP32 planes (rows layout): taps
-// outside the detector land in the 2-pixel border and are dropped when the
-// interior is added to the caller's stack.  Float atomics make the order of
-// the sums, and so their last bits, vary between runs.
-template <bool WCHECK>
-__global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
-{
-    int bid = blockIdx.x;
-    if (A.xcd_remap) {
-        const int per = gridDim.x >> 3;
-        bid = (bid & 7) * per + (bid >> 3);
-    }
-    const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
-    const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
-    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
-    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
-    const int tx = A.y_fastest ? t1 : t0;
-    const int ty = A.y_fastest ? t0 : t1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wx0 = tx * kTileX;
-    const int wy0 = ty * kTileY + wave * kWaveY;
-    const int x = wx0 + (lane % kWaveX);
-    const int y = wy0 + (lane / kWaveX);
-    const int zl0 = zc * kFusedZ;
-    const float xp = (float)x - A.c;
-    const float yp = (float)y - A.c;
-    const float zp0 = (float)(A.z_first + zl0) - A.c;
-    const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
-    const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
-    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
-    const bool corner_lane = lane < 8;
-
-    // the thread's voxel values (0 outside the volume)
-    float val[kFusedZ];
-    const bool inside = x < A.N && y < A.N;
-    const size_t slice = (size_t)A.N * A.N;
-    const float* src = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
-#pragma unroll
-    for (int i = 0; i < kFusedZ; ++i)
-        val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
-
-    const int Wp = A.Wp;
-    const uint32_t row_bytes = (uint32_t)Wp * 4u;
-    const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
-    const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
-    const char* plane = (const char*)A.img;
-    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const float* m = A.m[j];
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
-        if constexpr (!WCHECK) {
-            const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
-            const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
-            const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
-            const float cr = __builtin_amdgcn_rcpf(cw);
-            const float u = cu * cr, v = cv * cr;
-            if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
-                __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
-                continue;
-        }
-        const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
-        const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
-        const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
-#pragma unroll
-        for (int i = 0; i < kFusedZ; ++i) {
-            const float zp = zp0 + (float)i;
-            const float uw = fmaf(zp, m[2], bu);
-            const float vw = fmaf(zp, m[6], bv);
-            const float w = fmaf(zp, m[10], bw);
-            float r = __builtin_amdgcn_rcpf(w);
-            if (WCHECK) r = (w > 0.0f) ? r : 0.0f;
-            const float u = uw * r;
-            const float v = vw * r;
-            const float au = __builtin_amdgcn_fractf(u);
-            const float av = __builtin_amdgcn_fractf(v);
-            const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
-            const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
-            const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
-            const float s = val[i] * (r * r);
-            const float b = s * av;       // bottom row weight
-            const float a = s - b;        // top row weight
-            const float tr = a * au, br = b * au;
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b - br, rsrc, off, row_bytes, 0);
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(br, rsrc, off + 4u, row_bytes, 0);
-        }
-    }
-}
-
-hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
-{
-    dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
-    if (wcheck)
-        hipLaunchKernelGGL((fp_scatter_kernel<true>), grid, dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL((fp_scatter_kernel<false>), grid, dim3(kThreads), 0, s, a);
-    return hipGetLastError();
-}
-
-// LDS variant of the forward projection.  A workgroup owns a 16 x 16 x 16
-// voxel box (one column of 16 z per thread).  Per view the 8 projected box
-// corners bound the box's footprint on the detector (the projection of the
-// box lies in the hull of the corners); the workgroup accumulates its
-// scatter into an LDS tile covering that footprint (plus a 1-pixel margin
-// against rounding) and then adds the tile's non-zero pixels to the padded
-// plane with one global atomic each: about one global atomic per footprint
-// pixel instead of four per voxel.  A footprint larger than the tile falls
-// back to direct global atomics for that view.
-constexpr int kFpTile = 16;
-constexpr int kFpLds = 8192;  // floats of LDS tile
-
-__global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
-{
-    __shared__ float tile[kFpLds];
-    int bid = blockIdx.x;
-    if (A.xcd_remap) {
-        const int per = gridDim.x >> 3;
-        bid = (bid & 7) * per + (bid >> 3);
-    }
-    const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
-    const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
-    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
-    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
-    const int tx = A.y_fastest ? t1 : t0;
-    const int ty = A.y_fastest ? t0 : t1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int bx0 = tx * kFpTile, by0 = ty * kFpTile;
-    const int x = bx0 + (threadIdx.x % kFpTile);
-    const int y = by0 + (threadIdx.x / kFpTile);
-    const int zl0 = zc * kFusedZ;
-    const float xp = (float)x - A.c;
-    const float yp = (float)y - A.c;
-    const float zp0 = (float)(A.z_first + zl0) - A.c;
-    // lanes 0..7 of every wave hold the corners of the workgroup's box
-    const float cxp = (float)(bx0 + ((lane & 1) ? kFpTile - 1 : 0)) - A.c;
-    const float cyp = (float)(by0 + ((lane & 2) ? kFpTile - 1 : 0)) - A.c;
-    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
-    const bool corner_lane = lane < 8;
-
-    float val[kFusedZ];
-    const bool inside = x < A.N && y < A.N;
-    const size_t slice = (size_t)A.N * A.N;
-    const float* src = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
-#pragma unroll
-    for (int i = 0; i < kFusedZ; ++i)
-        val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
-
-    const int Wp = A.Wp;
-    const uint32_t row_bytes = (uint32_t)Wp * 4u;
-    const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
-    const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
-    const int lo_u = (int)A.lo_u, hi_u = (int)(A.hi_u - 0.5f);
-    const int lo_v = (int)A.lo_v, hi_v = (int)(A.hi_v - 0.5f);
-    const char* plane = (const char*)A.img;
-    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const float* m = A.m[j];
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
-        const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
-        const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
-        const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
-        const float cr = __builtin_amdgcn_rcpf(cw);
-        float umin = corner_lane ? cu * cr : INFINITY, umax = corner_lane ? cu * cr : -INFINITY;
-        float vmin = corner_lane ? cv * cr : INFINITY, vmax = corner_lane ? cv * cr : -INFINITY;
-#pragma unroll
-        for (int d = 1; d < 8; d <<= 1) {
-            umin = fminf(umin, __shfl_xor(umin, d));
-            umax = fmaxf(umax, __shfl_xor(umax, d));
-            vmin = fminf(vmin, __shfl_xor(vmin, d));
-            vmax = fmaxf(vmax, __shfl_xor(vmax, d));
-        }
-        umin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umin)));
-        umax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umax)));
-        vmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmin)));
-        vmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmax)));
-        // every wave computed the same corners: the decisions below agree
-        if (umax < A.skip_lo_u || umin > A.skip_hi_u || vmax < A.skip_lo_v || vmin > A.skip_hi_v)
-            continue;
-        const int U0 = max((int)floorf(umin) - 1, lo_u);
-        const int U1 = min((int)floorf(umax) + 2, hi_u + 1);
-        const int V0 = max((int)floorf(vmin) - 1, lo_v);
-        const int V1 = min((int)floorf(vmax) + 2, hi_v + 1);
-        const int TW = U1 - U0 + 1, TH = V1 - V0 + 1;
-        const bool use_lds = TW * TH <= kFpLds;
-        if (use_lds) {
-            for (int e = threadIdx.x; e < TW * TH; e += 256) tile[e] = 0.0f;
-            __syncthreads();
-        }
-        const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
-        const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
-        const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
-        const int last = TW * TH - TW - 2;
-#pragma unroll
-        for (int i = 0; i < kFusedZ; ++i) {
-            const float zp = zp0 + (float)i;
-            const float uw = fmaf(zp, m[2], bu);
-            const float vw = fmaf(zp, m[6], bv);
-            const float w = fmaf(zp, m[10], bw);
-            const float r = __builtin_amdgcn_rcpf(w);
-            const float u = uw * r;
-            const float v = vw * r;
-            const float au = __builtin_amdgcn_fractf(u);
-            const float av = __builtin_amdgcn_fractf(v);
-            const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
-            const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
-            const float s = val[i] * (r * r);
-            const float b = s * av;
-            const float a = s - b;
-            const float tr = a * au, br = b * au;
-            if (use_lds) {
-                // inside the tile by construction; the clamp only guards it
-                const int l = min(max((iv - V0) * TW + (iu - U0), 0), last);
-                atomicAdd(&tile[l], a - tr);
-                atomicAdd(&tile[l + 1], tr);
-                atomicAdd(&tile[l + TW], b - br);
-                atomicAdd(&tile[l + TW + 1], br);
-            } else {
-                const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b - br, rsrc, off, row_bytes, 0);
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(br, rsrc, off + 4u, row_bytes, 0);
-            }
-        }
-        if (use_lds) {
-            __syncthreads();
-            for (int rr = wave; rr < TH; rr += 4) {
-                const uint32_t row_off =
-                    (uint32_t)mad_i24(V0 + rr, Wp, U0) * 4u + centre_bytes;
-                for (int cc = lane; cc < TW; cc += 64) {
-                    const float t = tile[rr * TW + cc];
-                    if (t != 0.0f)
-                        __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(t, rsrc, row_off + 4u * cc,
-                                                                        0, 0);
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s)
-{
-    dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
-    hipLaunchKernelGGL(fp_lds_kernel, grid, dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void unstage_add_kernel(UnstageArgs a)
-{
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    const int k = blockIdx.y;
-    const int view = blockIdx.z;
-    if (j >= a.W) return;
-    const float v = a.planes[((size_t)view * a.Hp + k + kPad) * a.Wp + j + kPad];
-    a.dst[((size_t)view * a.H + k) * a.W + j] += v;
-}
-
-hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s)
-{
-    dim3 grid((a.W + 255) / 256, a.H, a.count);
-    hipLaunchKernelGGL(unstage_add_kernel, grid, dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void zero_kernel(float4* a, size_t n4)
-{
-    const size_t stride = (size_t)gridDim.x * 256;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride)
-        a[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-}
-
-// n must be a multiple of 4 and a 16-byte aligned
-hipError_t launch_zero(float* a, size_t n, hipStream_t st)
-{
-    size_t blocks = (n / 4 + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)a, n / 4);
     return hipGetLastError();
 }
 

@@ -23,9 +23,21 @@ enum StorageType { kF32 = 0, kF16 = 1, kBF16 = 2 };
 //   kRows : p(r, c)                                   (1 value)
 //   kPairs: p(r, c), p(r+1, c)                         (2 values)
 //   kQuads: p(r, c), p(r, c+1), p(r+1, c), p(r+1, c+1) (4 values)
+//   kDPairs: p(r, c), p(r+1, c) - p(r, c)              (2 values)
+//   kDQuads: p00, p10 - p00, p01 - p00, (p11 - p01) - (p10 - p00)
+//            with pRC = p(r+R, c+C)                   (4 values)
 // so that the four taps of a bilinear sample are two loads (rows) or one
-// load (pairs: 2 adjacent elements; quads: 1 element).
-enum Layout { kRows = 0, kPairs = 1, kQuads = 2 };
+// load (pairs, dpairs: 2 adjacent elements; quads, dquads: 1 element).
+// dpairs and dquads store the differences the interpolation needs (rounded
+// to the storage type): the bilinear sample then costs 4 (dpairs) or 3
+// (dquads) instructions instead of 6.
+enum Layout { kRows = 0, kPairs = 1, kQuads = 2, kDPairs = 3, kDQuads = 4 };
+
+// values per staged element
+__host__ __device__ constexpr int layout_width(int layout)
+{
+    return layout == kRows ? 1 : (layout == kQuads || layout == kDQuads) ? 4 : 2;
+}
 
 // Arguments of the fused kernel.  Matrices are in the centred index frame:
 // for voxel (x, y, z) with x' = x - c (likewise y', z'), (u'w, v'w, w) =

@@ -1,0 +1,295 @@
+// Forward projection kernels for gfx950: the exact transpose of the fused
+// backprojection, used as its adjoint (gradients through the backprojection)
+// and as a matched projector.
+#include "fdk_internal.h"
+#include "gfx950_util.h"
+
+namespace fdk {
+
+// ---------------------------------------------------------------------------
+// forward projection: the exact transpose of the backprojection
+// ---------------------------------------------------------------------------
+// Every voxel value times r^2 = 1/w^2 is spread onto the four taps the
+// backprojection reads, with the same bilinear weights (1-au)(1-av), au(1-av),
+// (1-au)av, au av.  The targets are padded FP32 planes (rows layout): taps
+// outside the detector land in the 2-pixel border and are dropped when the
+// interior is added to the caller's stack.  Float atomics make the order of
+// the sums, and so their last bits, vary between runs.
+template <bool WCHECK>
+__global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
+{
+    int bid = blockIdx.x;
+    if (A.xcd_remap) {
+        const int per = gridDim.x >> 3;
+        bid = (bid & 7) * per + (bid >> 3);
+    }
+    const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int tx = A.y_fastest ? t1 : t0;
+    const int ty = A.y_fastest ? t0 : t1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wx0 = tx * kTileX;
+    const int wy0 = ty * kTileY + wave * kWaveY;
+    const int x = wx0 + (lane % kWaveX);
+    const int y = wy0 + (lane / kWaveX);
+    const int zl0 = zc * kFusedZ;
+    const float xp = (float)x - A.c;
+    const float yp = (float)y - A.c;
+    const float zp0 = (float)(A.z_first + zl0) - A.c;
+    const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
+    const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
+    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
+    const bool corner_lane = lane < 8;
+
+    // the thread's voxel values (0 outside the volume)
+    float val[kFusedZ];
+    const bool inside = x < A.N && y < A.N;
+    const size_t slice = (size_t)A.N * A.N;
+    const float* src = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
+#pragma unroll
+    for (int i = 0; i < kFusedZ; ++i)
+        val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
+
+    const int Wp = A.Wp;
+    const uint32_t row_bytes = (uint32_t)Wp * 4u;
+    const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
+    const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
+    const char* plane = (const char*)A.img;
+    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
+        const float* m = A.m[j];
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
+        if constexpr (!WCHECK) {
+            const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
+            const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
+            const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
+            const float cr = __builtin_amdgcn_rcpf(cw);
+            const float u = cu * cr, v = cv * cr;
+            if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
+                __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
+                continue;
+        }
+        const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
+        const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
+        const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
+#pragma unroll
+        for (int i = 0; i < kFusedZ; ++i) {
+            const float zp = zp0 + (float)i;
+            const float uw = fmaf(zp, m[2], bu);
+            const float vw = fmaf(zp, m[6], bv);
+            const float w = fmaf(zp, m[10], bw);
+            float r = __builtin_amdgcn_rcpf(w);
+            if (WCHECK) r = (w > 0.0f) ? r : 0.0f;
+            const float u = uw * r;
+            const float v = vw * r;
+            const float au = __builtin_amdgcn_fractf(u);
+            const float av = __builtin_amdgcn_fractf(v);
+            const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
+            const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
+            const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
+            const float s = val[i] * (r * r);
+            const float b = s * av;       // bottom row weight
+            const float a = s - b;        // top row weight
+            const float tr = a * au, br = b * au;
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b - br, rsrc, off, row_bytes, 0);
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(br, rsrc, off + 4u, row_bytes, 0);
+        }
+    }
+}
+
+hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
+{
+    dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
+    if (wcheck)
+        hipLaunchKernelGGL((fp_scatter_kernel<true>), grid, dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((fp_scatter_kernel<false>), grid, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// LDS variant of the forward projection.  A workgroup owns a 16 x 16 x 16
+// voxel box (one column of 16 z per thread).  Per view the 8 projected box
+// corners bound the box's footprint on the detector (the projection of the
+// box lies in the hull of the corners); the workgroup accumulates its
+// scatter into an LDS tile covering that footprint (plus a 1-pixel margin
+// against rounding) and then adds the tile's non-zero pixels to the padded
+// plane with one global atomic each: about one global atomic per footprint
+// pixel instead of four per voxel.  A footprint larger than the tile falls
+// back to direct global atomics for that view.
+constexpr int kFpTile = 16;
+constexpr int kFpLds = 8192;  // floats of LDS tile
+
+__global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
+{
+    __shared__ float tile[kFpLds];
+    int bid = blockIdx.x;
+    if (A.xcd_remap) {
+        const int per = gridDim.x >> 3;
+        bid = (bid & 7) * per + (bid >> 3);
+    }
+    const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
+    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int tx = A.y_fastest ? t1 : t0;
+    const int ty = A.y_fastest ? t0 : t1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int bx0 = tx * kFpTile, by0 = ty * kFpTile;
+    const int x = bx0 + (threadIdx.x % kFpTile);
+    const int y = by0 + (threadIdx.x / kFpTile);
+    const int zl0 = zc * kFusedZ;
+    const float xp = (float)x - A.c;
+    const float yp = (float)y - A.c;
+    const float zp0 = (float)(A.z_first + zl0) - A.c;
+    // lanes 0..7 of every wave hold the corners of the workgroup's box
+    const float cxp = (float)(bx0 + ((lane & 1) ? kFpTile - 1 : 0)) - A.c;
+    const float cyp = (float)(by0 + ((lane & 2) ? kFpTile - 1 : 0)) - A.c;
+    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
+    const bool corner_lane = lane < 8;
+
+    float val[kFusedZ];
+    const bool inside = x < A.N && y < A.N;
+    const size_t slice = (size_t)A.N * A.N;
+    const float* src = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
+#pragma unroll
+    for (int i = 0; i < kFusedZ; ++i)
+        val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
+
+    const int Wp = A.Wp;
+    const uint32_t row_bytes = (uint32_t)Wp * 4u;
+    const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
+    const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
+    const int lo_u = (int)A.lo_u, hi_u = (int)(A.hi_u - 0.5f);
+    const int lo_v = (int)A.lo_v, hi_v = (int)(A.hi_v - 0.5f);
+    const char* plane = (const char*)A.img;
+    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
+        const float* m = A.m[j];
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
+        const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
+        const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
+        const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
+        const float cr = __builtin_amdgcn_rcpf(cw);
+        float umin = corner_lane ? cu * cr : INFINITY, umax = corner_lane ? cu * cr : -INFINITY;
+        float vmin = corner_lane ? cv * cr : INFINITY, vmax = corner_lane ? cv * cr : -INFINITY;
+#pragma unroll
+        for (int d = 1; d < 8; d <<= 1) {
+            umin = fminf(umin, __shfl_xor(umin, d));
+            umax = fmaxf(umax, __shfl_xor(umax, d));
+            vmin = fminf(vmin, __shfl_xor(vmin, d));
+            vmax = fmaxf(vmax, __shfl_xor(vmax, d));
+        }
+        umin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umin)));
+        umax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umax)));
+        vmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmin)));
+        vmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmax)));
+        // every wave computed the same corners: the decisions below agree
+        if (umax < A.skip_lo_u || umin > A.skip_hi_u || vmax < A.skip_lo_v || vmin > A.skip_hi_v)
+            continue;
+        const int U0 = max((int)floorf(umin) - 1, lo_u);
+        const int U1 = min((int)floorf(umax) + 2, hi_u + 1);
+        const int V0 = max((int)floorf(vmin) - 1, lo_v);
+        const int V1 = min((int)floorf(vmax) + 2, hi_v + 1);
+        const int TW = U1 - U0 + 1, TH = V1 - V0 + 1;
+        const bool use_lds = TW * TH <= kFpLds;
+        if (use_lds) {
+            for (int e = threadIdx.x; e < TW * TH; e += 256) tile[e] = 0.0f;
+            __syncthreads();
+        }
+        const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
+        const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
+        const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
+        const int last = TW * TH - TW - 2;
+#pragma unroll
+        for (int i = 0; i < kFusedZ; ++i) {
+            const float zp = zp0 + (float)i;
+            const float uw = fmaf(zp, m[2], bu);
+            const float vw = fmaf(zp, m[6], bv);
+            const float w = fmaf(zp, m[10], bw);
+            const float r = __builtin_amdgcn_rcpf(w);
+            const float u = uw * r;
+            const float v = vw * r;
+            const float au = __builtin_amdgcn_fractf(u);
+            const float av = __builtin_amdgcn_fractf(v);
+            const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
+            const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
+            const float s = val[i] * (r * r);
+            const float b = s * av;
+            const float a = s - b;
+            const float tr = a * au, br = b * au;
+            if (use_lds) {
+                // inside the tile by construction; the clamp only guards it
+                const int l = min(max((iv - V0) * TW + (iu - U0), 0), last);
+                atomicAdd(&tile[l], a - tr);
+                atomicAdd(&tile[l + 1], tr);
+                atomicAdd(&tile[l + TW], b - br);
+                atomicAdd(&tile[l + TW + 1], br);
+            } else {
+                const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b - br, rsrc, off, row_bytes, 0);
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(br, rsrc, off + 4u, row_bytes, 0);
+            }
+        }
+        if (use_lds) {
+            __syncthreads();
+            for (int rr = wave; rr < TH; rr += 4) {
+                const uint32_t row_off =
+                    (uint32_t)mad_i24(V0 + rr, Wp, U0) * 4u + centre_bytes;
+                for (int cc = lane; cc < TW; cc += 64) {
+                    const float t = tile[rr * TW + cc];
+                    if (t != 0.0f)
+                        __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(t, rsrc, row_off + 4u * cc,
+                                                                        0, 0);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s)
+{
+    dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
+    hipLaunchKernelGGL(fp_lds_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void unstage_add_kernel(UnstageArgs a)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    const int view = blockIdx.z;
+    if (j >= a.W) return;
+    const float v = a.planes[((size_t)view * a.Hp + k + kPad) * a.Wp + j + kPad];
+    a.dst[((size_t)view * a.H + k) * a.W + j] += v;
+}
+
+hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s)
+{
+    dim3 grid((a.W + 255) / 256, a.H, a.count);
+    hipLaunchKernelGGL(unstage_add_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(float4* a, size_t n4)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride)
+        a[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// n must be a multiple of 4 and a 16-byte aligned
+hipError_t launch_zero(float* a, size_t n, hipStream_t st)
+{
+    size_t blocks = (n / 4 + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, (float4*)a, n / 4);
+    return hipGetLastError();
+}
+
+}  // namespace fdk

@@ -18,7 +18,7 @@ theta holds the ramp's frequency response on bins k = 0..1023 of a
 Ram-Lak value.  h spans the 2W-1 taps a linear convolution of a W-sample row
 needs; M maps theta to them (the inverse real DFT).  At initialisation
 (theta = Ram-Lak, lambda = 1, W3 = b3 = 0) the model is exactly plain FBP,
-which stays the fallback and the judge.
+the baseline a trained filter is compared with.
 
 Training minimises the mean squared error between vol and the voxelised
 phantom inside the field of view.  The gradient of vol is mapped back by the
@@ -95,6 +95,10 @@ def ramp_basis(g: Geometry):
     n = -(W-1) .. W-1, and the Ram-Lak initialisation of theta."""
     L = FFT_LEN
     W = g.W
+    if 2 * W - 1 > L:
+        # the 2W-1 taps would wrap around the L-periodic grid and alias
+        raise ValueError(f"learned filter: detector rows of {W} pixels need more than "
+                         f"{L} DFT bins (at most {(L + 1) // 2} pixels)")
     tau = g.tau
     n = np.arange(-(W - 1), W)
     # Ram-Lak taps on |n| <= W-1, zero elsewhere on the L-periodic grid

@@ -99,3 +99,15 @@ def test_batch_setting():
     assert L.fdk_set_batch(65) == fdk.FDK_ERR_INVALID_ARG
     assert L.fdk_set_batch(7) == 7
     assert L.fdk_set_batch(old) == old
+
+
+def test_layout_setting():
+    L = fdk.lib()
+    old = L.fdk_set_layout(-1)
+    assert 0 <= old <= 4
+    assert L.fdk_set_layout(5) == fdk.FDK_ERR_INVALID_ARG
+    assert L.fdk_set_layout(-2) == fdk.FDK_ERR_INVALID_ARG
+    for name, code in fdk.LAYOUTS.items():
+        assert fdk.set_layout(name) == name
+        assert L.fdk_set_layout(-1) == code
+    assert L.fdk_set_layout(old) == old

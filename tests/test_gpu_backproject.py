@@ -102,6 +102,33 @@ def test_fused_is_deterministic(torch_dev, fdk_mod, stack):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("layout", ["rows", "pairs", "quads", "dpairs", "dquads"])
+@pytest.mark.parametrize("dtype_name", ["float32", "float16", "bfloat16"])
+def test_every_layout_and_storage_parity_128(torch_dev, fdk_mod, stack, ref128, layout,
+                                              dtype_name):
+    """Each staged layout (plain taps or stored differences) and storage type
+    against the oracle on the full 496-view stack at 128^3: FP32 storage to
+    1e-5, FP16/BF16 storage to 1e-3."""
+    torch, dev = torch_dev
+    geom, proj, proj_d = stack
+    vs, o = synth.volume_frame(128)
+    old = fdk_mod.set_layout(None)
+    try:
+        fdk_mod.set_layout(layout)
+        vol = torch.zeros(128, 128, 128, device=dev)
+        if dtype_name == "float32":
+            fdk_mod.backproject(vol, proj_d, geom.P, vs, o)
+        else:
+            st, scale = fdk_mod.to_storage(proj_d, getattr(torch, dtype_name))
+            fdk_mod.backproject(vol, st, geom.P, vs, o, view_scale=scale)
+        torch.cuda.synchronize()
+    finally:
+        fdk_mod.set_layout(old)
+    err = oracle.rel_rmse(vol.cpu().numpy(), ref128)
+    print(f"layout {layout} {dtype_name}: relRMSE {err:.3e}", flush=True)
+    assert err <= (FP32_TOL if dtype_name == "float32" else 1e-3)
+
+
 @pytest.mark.parametrize("split", [64, 100, 1])
 def test_views_split_over_calls_accumulate(torch_dev, fdk_mod, stack, split):
     torch, dev = torch_dev

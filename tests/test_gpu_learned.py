@@ -203,7 +203,7 @@ def test_model_initialisation_is_plain_fbp(env):
 def test_learned_filter_beats_plain_fbp_on_held_out_phantoms(env):
     """Train on 32 seeded phantoms (two passes, 62 views of 624x480, 128^3,
     exact line integrals), then reconstruct two held-out phantoms: the
-    learned filter's masked RMSE must be below plain FBP's (the judge)."""
+    learned filter's masked RMSE must be at least 2 % below plain FBP's."""
     torch, fdk, GL, dev = env
     g = synth.cone_beam_geometry(n_views=62, H=480, W=624, pixel=0.616)
     geo = GL.geometry_from(g)
