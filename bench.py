@@ -120,13 +120,15 @@ def bench_forward(args, torch, fdk, synth, dev):
         f"{launches} scatter launches, {kms / max(launches, 1):.3f} ms each")
     # oracle on a bounded sample: the same volume, the first Vs views
     Vs = 16
-    vol_h = vol.double().cpu().numpy()
-    t0 = time.perf_counter()
-    ref = oracle.forward_project(vol_h, geom.P[:Vs], H, W, vs, origin)
-    tc = time.perf_counter() - t0
-    step()
-    torch.cuda.synchronize()
-    err = oracle.rel_rmse(proj[:Vs].double().cpu().numpy(), ref)
+    tc, err = None, None
+    if not args.no_extras:
+        vol_h = vol.double().cpu().numpy()
+        t0 = time.perf_counter()
+        ref = oracle.forward_project(vol_h, geom.P[:Vs], H, W, vs, origin)
+        tc = time.perf_counter() - t0
+        step()
+        torch.cuda.synchronize()
+        err = oracle.rel_rmse(proj[:Vs].double().cpu().numpy(), ref)
     out = _common(
         args, "forward projection voxel-view pairs/s at 256^3 x 248 views of 624x480",
         round(updates / t / 1e9, 2), "GUP/s", t, "f32",
@@ -135,10 +137,12 @@ def bench_forward(args, torch, fdk, synth, dev):
          "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
          "kernel": "fp_lds_kernel", "launches_per_step": launches // args.steps,
          "kernel_ms_per_step": round(kms / args.steps, 3)},
+        None if tc is None else
         {"value": round(float(N) ** 3 * Vs / tc / 1e9, 4), "unit": "GUP/s",
          "cores": oracle.threads(), "kind": "oracle",
          "sample": f"the {N}^3 volume onto the first {Vs} of {V} views, FP64, {tc:.1f} s"})
-    out["rel_rmse_vs_oracle"] = float(f"{err:.3e}")
+    if err is not None:
+        out["rel_rmse_vs_oracle"] = float(f"{err:.3e}")
     return out
 
 
@@ -171,12 +175,14 @@ def bench_prefilter(args, torch, fdk, synth, dev):
     ach = flop * args.steps / ks / 1e12
     log(f"prefilter: {t * 1e3:.2f} ms/step, {ach:.2f} TFLOP/s FP64")
     Vs = 2
-    t0 = time.perf_counter()
-    ref = fdk_prefilter(li[:Vs], geom.betas[:Vs], delta, geom.dbeta, geom.sid, geom.sdd,
-                        geom.pixel)
-    tc = time.perf_counter() - t0
-    err = float(np.sqrt(((out_d[:Vs].double().cpu().numpy() - ref) ** 2).sum()
-                        / (ref ** 2).sum()))
+    tc, err = None, None
+    if not args.no_extras:
+        t0 = time.perf_counter()
+        ref = fdk_prefilter(li[:Vs], geom.betas[:Vs], delta, geom.dbeta, geom.sid, geom.sdd,
+                            geom.pixel)
+        tc = time.perf_counter() - t0
+        err = float(np.sqrt(((out_d[:Vs].double().cpu().numpy() - ref) ** 2).sum()
+                            / (ref ** 2).sum()))
     out = _common(
         args, "pre-filtered detector rows/s, 496 views of 1248x960", round(rows / t / 1e6, 3),
         "Mrow/s", t, "f64",
@@ -185,10 +191,12 @@ def bench_prefilter(args, torch, fdk, synth, dev):
          "frac": round(ach / 78.6, 4), "traffic": None, "kernel": "prefilter_kernel",
          "launches_per_step": launches // args.steps,
          "kernel_ms_per_step": round(kms / args.steps, 3)},
+        None if tc is None else
         {"value": round(Vs * H / tc / 1e6, 5), "unit": "Mrow/s", "cores": 1, "kind": "oracle",
          "sample": f"the first {Vs} of {V} views ({Vs * H} rows), np.convolve in FP64, "
                    f"{tc:.1f} s"})
-    out["rel_rmse_vs_oracle"] = float(f"{err:.3e}")
+    if err is not None:
+        out["rel_rmse_vs_oracle"] = float(f"{err:.3e}")
     return out
 
 
@@ -233,14 +241,16 @@ def bench_learn_step(args, torch, fdk, synth, dev):
     log(f"learn step: {t * 1e3:.1f} ms; conv 32->32: {conv_s * 1e3:.3f} ms, {ach:.1f} TFLOP/s")
     # oracle step on a bounded sample: 2 of the 62 views
     Vs = 2
-    params = {n: getattr(model, n).double().cpu().numpy() for n in model.params}
-    params["lam"] = params["lam"][:Vs]
-    T = GL.weight_table(geo)[:Vs]
-    M, _, _ = GL.ramp_basis(geo)
-    t0 = time.perf_counter()
-    OL.loss_and_grads(params, p[:Vs].double().cpu().numpy(), T, M, geo.P[:Vs], N, vs, o,
-                      model.sigma, gt.double().cpu().numpy(), mask.double().cpu().numpy())
-    tc = time.perf_counter() - t0
+    tc = None
+    if not args.no_extras:
+        params = {n: getattr(model, n).double().cpu().numpy() for n in model.params}
+        params["lam"] = params["lam"][:Vs]
+        T = GL.weight_table(geo)[:Vs]
+        M, _, _ = GL.ramp_basis(geo)
+        t0 = time.perf_counter()
+        OL.loss_and_grads(params, p[:Vs].double().cpu().numpy(), T, M, geo.P[:Vs], N, vs, o,
+                          model.sigma, gt.double().cpu().numpy(), mask.double().cpu().numpy())
+        tc = time.perf_counter() - t0
     out = _common(
         args, "learned-filter training steps/s at 128^3 x 62 views of 624x480",
         round(1.0 / t, 3), "steps/s", t, "f32",
@@ -250,6 +260,7 @@ def bench_learn_step(args, torch, fdk, synth, dev):
          "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
          "kernel": "conv_short_kernel (32->32, K=9)",
          "kernel_ms": round(conv_s * 1e3, 3)},
+        None if tc is None else
         {"value": round(Vs / geo.V / tc, 5), "unit": "steps/s", "cores": oracle.threads(),
          "kind": "oracle",
          "sample": f"FP64 oracle step on {Vs} of {geo.V} views ({tc:.1f} s), scaled by "
