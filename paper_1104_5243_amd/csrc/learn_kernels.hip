@@ -105,9 +105,254 @@ __global__ __launch_bounds__(256) void conv_long_kernel(LearnConvArgs a)
     *o = v;
 }
 
+// ---------------------------------------------------------------------------
+// MFMA path for the wide layers (cin = cout = 32, 9 taps)
+// ---------------------------------------------------------------------------
+// Both the convolution and its weight gradient are dense contractions:
+//   out[co][j]   = sum over (ci, t) of W[co][ci][t] x[ci][j + t - pad]
+//                  (M = cout, N = positions, K = cin * taps)
+//   dW[co][ci][t] = sum over positions p of dy[co][p] x[ci][p + t - pad]
+//                  (M = cout, N = cin * taps, K = positions)
+// and run on v_mfma_f32_16x16x4_f32 (FP32 operands and accumulation, so the
+// results keep FP32 accuracy).  Operand layout of that instruction: lane l
+// holds A[m = l % 16][k = l / 16] and B[k = l / 16][n = l % 16]; the 4
+// results of lane l are D[m = 4 (l / 16) + i][n = l % 16], i = 0..3.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf4 mfma16x16x4(float a, float b, mf4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// LDS pitch >= n that is 16 (mod 32) or 2 (mod 32): the fragment reads of a
+// wave then touch distinct banks within each half-wave.
+__host__ __device__ constexpr int pitch16(int n) { return ((n + 15) / 32) * 32 + 16; }
+__host__ __device__ constexpr int pitch2(int n) { return ((n + 29) / 32) * 32 + 2; }
+
+// Convolution: a block owns 128 positions of one row at a time (wave w:
+// positions 32 w .. 32 w + 31, two 16-wide n-tiles) for all output
+// channels (two 16-wide m-tiles); the weights, stored as A fragments, stay
+// in LDS for the block's lifetime; it walks the chunks of all rows.
+template <int CIN, int COUT, int KT>
+struct ConvMfma {
+    static constexpr int kChunk = 128;
+    static constexpr int kMT = COUT / 16;
+    static constexpr int kC4 = CIN / 4;
+    static constexpr int kSteps = kC4 * KT;
+    static constexpr int kSpan = kChunk + KT - 1;
+    static constexpr int kPitch = pitch16(kSpan);
+    static constexpr int kWeights = kMT * kSteps * 64;
+    static constexpr size_t lds_bytes() { return (size_t)(kWeights + CIN * kPitch) * 4; }
+    static_assert(CIN % 4 == 0 && COUT % 16 == 0, "channel counts");
+};
+
+template <int CIN, int COUT, int KT>
+__global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chunks_per_row,
+                                                        int total_chunks)
+{
+    using C = ConvMfma<CIN, COUT, KT>;
+    extern __shared__ float lds[];
+    float* wl = lds;                 // A fragments: [mt][step][lane]
+    float* xs = lds + C::kWeights;   // input tile: [ci][kPitch]
+    const int l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    for (int e = threadIdx.x; e < C::kWeights; e += 256) {
+        const int ll = e & 63, f = e >> 6;
+        const int mt = f / C::kSteps, st = f - mt * C::kSteps;
+        const int c4 = st / KT, t = st - c4 * KT;
+        wl[e] = conv_weight(a, mt * 16 + (ll & 15), 4 * c4 + (ll >> 4), t);
+    }
+    const float* xb = xs + (l >> 4) * C::kPitch + w * 32 + (l & 15);
+    for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
+        const int row = c / chunks_per_row;
+        const int j0 = (c - row * chunks_per_row) * C::kChunk;
+        const float* in = a.in + (size_t)row * CIN * a.W;
+        __syncthreads();  // the previous chunk's fragment reads are done
+        for (int e = threadIdx.x; e < CIN * C::kSpan; e += 256) {
+            const int ci = e / C::kSpan, sp = e - ci * C::kSpan;
+            const int j = j0 + sp - a.pad;
+            xs[ci * C::kPitch + sp] = (j >= 0 && j < a.W) ? in[(size_t)ci * a.W + j] : 0.0f;
+        }
+        __syncthreads();
+        mf4 acc[C::kMT][2];
+#pragma unroll
+        for (int mt = 0; mt < C::kMT; ++mt)
+            acc[mt][0] = acc[mt][1] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c4 = 0; c4 < C::kC4; ++c4) {
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const int st = c4 * KT + t;
+                const float b0 = xb[c4 * 4 * C::kPitch + t];
+                const float b1 = xb[c4 * 4 * C::kPitch + t + 16];
+#pragma unroll
+                for (int mt = 0; mt < C::kMT; ++mt) {
+                    const float av = wl[(mt * C::kSteps + st) * 64 + l];
+                    acc[mt][0] = mfma16x16x4(av, b0, acc[mt][0]);
+                    acc[mt][1] = mfma16x16x4(av, b1, acc[mt][1]);
+                }
+            }
+        }
+        float* out = a.out + (size_t)row * COUT * a.W;
+#pragma unroll
+        for (int mt = 0; mt < C::kMT; ++mt) {
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const int j = j0 + w * 32 + nt * 16 + (l & 15);
+                if (j >= a.W) continue;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int co = mt * 16 + 4 * (l >> 4) + i;
+                    float v = acc[mt][nt][i] + (a.bias ? a.bias[co] : 0.0f);
+                    float* o = out + (size_t)co * a.W + j;
+                    if (a.accumulate) v += *o;
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    *o = v;
+                }
+            }
+        }
+    }
+}
+
+// Weight gradient: a block walks chunks of 64 positions (16 k-steps); the
+// 32 x 288 result (columns n = t * CIN + ci) is split over the 4 waves by
+// n-tile (wave w: n-tiles w, w + 4, ...).  The MFMA accumulators are added
+// into FP64 sums after every chunk, the bias gradient is summed in FP64,
+// and the per-block sums go to the workspace for the fixed-order reduction.
+template <int CIN, int COUT, int KT>
+struct WgradMfma {
+    static constexpr int kChunk = 64;
+    static constexpr int kMT = COUT / 16;
+    static constexpr int kNT = CIN * KT / 16;
+    static constexpr int kNTW = (kNT + 3) / 4;  // n-tiles per wave (at most)
+    static constexpr int kSpan = kChunk + KT - 1;
+    static constexpr int kPitchX = pitch2(kSpan);
+    static constexpr int kPitchD = pitch2(kChunk);
+    static constexpr size_t lds_bytes()
+    {
+        return (size_t)(COUT * kPitchD + CIN * kPitchX) * 4 + 256 * sizeof(double);
+    }
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel counts");
+};
+
+template <int CIN, int COUT, int KT>
+__global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int chunks_per_row,
+                                                         int total_chunks)
+{
+    using G = WgradMfma<CIN, COUT, KT>;
+    extern __shared__ float lds[];
+    float* dy = lds;                          // [co][kPitchD]
+    float* xs = lds + COUT * G::kPitchD;      // [ci][kPitchX]
+    double* red = (double*)(xs + CIN * G::kPitchX);
+    const int l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    // per n-tile of this wave: offset of lane l's B fragment in the x tile
+    int boff[G::kNTW];
+#pragma unroll
+    for (int k = 0; k < G::kNTW; ++k) {
+        const int n0 = (w + 4 * k) * 16;
+        const int t = n0 / CIN, ci = n0 % CIN + (l & 15);
+        boff[k] = ci * G::kPitchX + t + (l >> 4);
+    }
+    const int aoff = (l & 15) * G::kPitchD + (l >> 4);
+    mf4 acc[G::kMT][G::kNTW];
+    double sum[G::kMT][G::kNTW][4];
+#pragma unroll
+    for (int mt = 0; mt < G::kMT; ++mt)
+#pragma unroll
+        for (int k = 0; k < G::kNTW; ++k) {
+            acc[mt][k] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sum[mt][k][i] = 0.0;
+        }
+    double accb = 0.0;  // bias gradient: thread sums co = tid / 8, positions (tid % 8) * 8 ..
+    for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
+        const int row = c / chunks_per_row;
+        const int j0 = (c - row * chunks_per_row) * G::kChunk;
+        const float* drow = a.dout + (size_t)row * COUT * a.W;
+        const float* xrow = a.in + (size_t)row * CIN * a.W;
+        __syncthreads();
+        for (int e = threadIdx.x; e < COUT * G::kChunk; e += 256) {
+            const int co = e / G::kChunk, p = e - co * G::kChunk;
+            const int j = j0 + p;
+            dy[co * G::kPitchD + p] = (j < a.W) ? drow[(size_t)co * a.W + j] : 0.0f;
+        }
+        for (int e = threadIdx.x; e < CIN * G::kSpan; e += 256) {
+            const int ci = e / G::kSpan, sp = e - ci * G::kSpan;
+            const int j = j0 + sp - a.pad;
+            xs[ci * G::kPitchX + sp] = (j >= 0 && j < a.W) ? xrow[(size_t)ci * a.W + j] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < G::kChunk / 4; ++st) {
+            float av[G::kMT];
+#pragma unroll
+            for (int mt = 0; mt < G::kMT; ++mt) av[mt] = dy[aoff + mt * 16 * G::kPitchD + 4 * st];
+#pragma unroll
+            for (int k = 0; k < G::kNTW; ++k) {
+                if (w + 4 * k < G::kNT) {
+                    const float bv = xs[boff[k] + 4 * st];
+#pragma unroll
+                    for (int mt = 0; mt < G::kMT; ++mt) acc[mt][k] = mfma16x16x4(av[mt], bv, acc[mt][k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < G::kMT; ++mt)
+#pragma unroll
+            for (int k = 0; k < G::kNTW; ++k) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sum[mt][k][i] += (double)acc[mt][k][i];
+                acc[mt][k] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        if (threadIdx.x < COUT * 8) {
+            const float* d = dy + (threadIdx.x >> 3) * G::kPitchD + (threadIdx.x & 7) * 8;
+            double sb = 0.0;
+#pragma unroll
+            for (int p = 0; p < 8; ++p) sb += (double)d[p];
+            accb += sb;
+        }
+    }
+    const int nw = COUT * CIN * KT;
+    double* part = a.part + (size_t)blockIdx.x * (nw + COUT);
+#pragma unroll
+    for (int mt = 0; mt < G::kMT; ++mt)
+#pragma unroll
+        for (int k = 0; k < G::kNTW; ++k) {
+            if (w + 4 * k >= G::kNT) continue;
+            const int n = (w + 4 * k) * 16 + (l & 15);
+            const int t = n / CIN, ci = n % CIN;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = mt * 16 + 4 * (l >> 4) + i;
+                part[((size_t)co * CIN + ci) * KT + t] = sum[mt][k][i];
+            }
+        }
+    red[threadIdx.x] = accb;
+    __syncthreads();
+    if (threadIdx.x < COUT) {
+        double sb = 0.0;
+        for (int q = 0; q < 8; ++q) sb += red[threadIdx.x * 8 + q];
+        part[nw + threadIdx.x] = sb;
+    }
+}
+
+// the shapes the MFMA path takes
+__host__ __device__ constexpr bool mfma_shape(int cin, int cout, int K)
+{
+    return cin == 32 && cout == 32 && K == 9;
+}
+
 hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s)
 {
-    if (a.K <= kMaxShortK) {
+    if (mfma_shape(a.cin, a.cout, a.K)) {
+        using C = ConvMfma<32, 32, 9>;
+        const int cpr = (a.W + C::kChunk - 1) / C::kChunk;
+        const int total = a.rows * cpr;
+        const int grid = total < 1024 ? total : 1024;
+        hipLaunchKernelGGL((conv_mfma_kernel<32, 32, 9>), dim3(grid), dim3(256), C::lds_bytes(), s,
+                           a, cpr, total);
+    } else if (a.K <= kMaxShortK) {
         dim3 grid((a.W + kShortTile - 1) / kShortTile, a.rows);
         const size_t lds = (size_t)a.cin * (kShortTile + a.K - 1) * sizeof(float);
         hipLaunchKernelGGL(conv_short_kernel, grid, dim3(256), lds, s, a);
@@ -204,9 +449,16 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(LearnGradArgs a, int 
 
 hipError_t launch_wgrad(const LearnGradArgs& a, int nblocks, hipStream_t s)
 {
-    const size_t lds =
-        (size_t)(a.cout * kGradChunk + a.cin * (kGradChunk + a.K - 1)) * sizeof(float);
-    hipLaunchKernelGGL(wgrad_partial_kernel, dim3(nblocks), dim3(256), lds, s, a);
+    if (mfma_shape(a.cin, a.cout, a.K)) {
+        using G = WgradMfma<32, 32, 9>;
+        const int cpr = (a.W + G::kChunk - 1) / G::kChunk;
+        hipLaunchKernelGGL((wgrad_mfma_kernel<32, 32, 9>), dim3(nblocks), dim3(256), G::lds_bytes(),
+                           s, a, cpr, a.rows * cpr);
+    } else {
+        const size_t lds =
+            (size_t)(a.cout * kGradChunk + a.cin * (kGradChunk + a.K - 1)) * sizeof(float);
+        hipLaunchKernelGGL(wgrad_partial_kernel, dim3(nblocks), dim3(256), lds, s, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int n = a.cout * a.cin * a.K + a.cout;

@@ -69,6 +69,46 @@ def test_conv_short_forward_adjoint_wgrad(env, cin, cout, W, rows, relu):
     assert rel(out2.cpu().numpy(), out.cpu().numpy() + base) <= 1e-5
 
 
+@pytest.mark.parametrize("W,rows,pad", [(624, 220, 4), (129, 6, 2), (1, 5, 4), (200, 300, 4)])
+def test_conv_mfma_path_shapes(env, W, rows, pad):
+    """The 32 -> 32 channel, 9-tap layers run on matrix cores: forward,
+    transposed and weight gradient against the oracle, with ragged tails
+    (W not a multiple of the 128- and 64-position chunks) and more chunks
+    than blocks (each block walks several)."""
+    torch, fdk, GL, dev = env
+    rng = np.random.default_rng(W * 1000 + rows)
+    cin = cout = 32
+    K = 9
+    x = rng.standard_normal((rows, cin, W)).astype(np.float32)
+    w = (rng.standard_normal((cout, cin, K)) * 0.1).astype(np.float32)
+    b = rng.standard_normal(cout).astype(np.float32)
+    dy = rng.standard_normal((rows, cout, W)).astype(np.float32)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    out = torch.empty(rows, cout, W, device=dev)
+    fdk.conv_rows(out, T(x), T(w), T(b), rows, W, cin, cout, K, pad, fdk.CONV_RELU)
+    ref = np.maximum(OL.conv(x.astype(np.float64), w.astype(np.float64), b, pad), 0)
+    e_fwd = rel(out.cpu().numpy(), ref)
+    dx = torch.empty(rows, cin, W, device=dev)
+    fdk.conv_rows(dx, T(dy), T(w), None, rows, W, cout, cin, K, K - 1 - pad, fdk.CONV_TRANSPOSE)
+    e_adj = rel(dx.cpu().numpy(), OL.conv_adjoint(dy.astype(np.float64), w.astype(np.float64),
+                                                  pad))
+    dw = torch.empty(cout, cin, K, device=dev)
+    db = torch.empty(cout, device=dev)
+    ws = torch.empty(fdk.conv_rows_wgrad_workspace(cin, cout, K) // 4, device=dev)
+    fdk.conv_rows_wgrad(dw, db, T(dy), T(x), rows, W, cin, cout, K, pad, ws)
+    rdw, rdb = OL.conv_wgrad(dy.astype(np.float64), x.astype(np.float64), K, pad)
+    torch.cuda.synchronize()
+    e_dw, e_db = rel(dw.cpu().numpy(), rdw), rel(db.cpu().numpy(), rdb)
+    print(f"mfma conv W={W} rows={rows} pad={pad}: fwd {e_fwd:.2e} adj {e_adj:.2e} "
+          f"dW {e_dw:.2e} db {e_db:.2e}", flush=True)
+    assert max(e_fwd, e_adj, e_dw, e_db) <= 1e-5
+    # the weight gradient is reduced in a fixed order: two calls agree bit for bit
+    dw2 = torch.empty_like(dw)
+    fdk.conv_rows_wgrad(dw2, None, T(dy), T(x), rows, W, cin, cout, K, pad, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(dw, dw2)
+
+
 @pytest.mark.parametrize("W,rows", [(100, 7), (624, 3)])
 def test_conv_long_forward_wgrad(env, W, rows):
     torch, fdk, GL, dev = env
