@@ -146,7 +146,7 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int n, floa
                        float b2, float eps, int step, hipStream_t s);
 hipError_t launch_mse(float* grad, float* loss, double* part, int nparts, const float* a,
                       const float* b, size_t n, hipStream_t s);
-constexpr int kGradBlocks = 256;  // partial-sum blocks of the weight gradients
+constexpr int kGradBlocks = 1024;  // partial-sum blocks of the weight gradients
 constexpr int kMseParts = 1024;
 
 #ifndef FDK_FUSED_Z

@@ -343,8 +343,67 @@ __host__ __device__ constexpr bool mfma_shape(int cin, int cout, int K)
     return cin == 32 && cout == 32 && K == 9;
 }
 
+// ---------------------------------------------------------------------------
+// narrow layers (one channel in or out, 9 taps): memory-bound
+// ---------------------------------------------------------------------------
+// One thread per output position, 256 positions per block, the input tile
+// (CIN x (256 + KT - 1)) in LDS; the weights are wave-uniform (compile-time
+// indices, scalar loads).  CIN = 1: the thread forms all COUT outputs from
+// its KT inputs; COUT = 1: it sums CIN x KT products.
+template <int CIN, int COUT, int KT>
+__global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
+{
+    constexpr int kSpan = 256 + KT - 1;
+    __shared__ float tile[CIN * kSpan];
+    const int row = blockIdx.y;
+    const int j0 = blockIdx.x * 256;
+    const float* in = a.in + (size_t)row * CIN * a.W;
+    for (int e = threadIdx.x; e < CIN * kSpan; e += 256) {
+        const int ci = e / kSpan, sp = e - ci * kSpan;
+        const int j = j0 + sp - a.pad;
+        tile[e] = (j >= 0 && j < a.W) ? in[(size_t)ci * a.W + j] : 0.0f;
+    }
+    __syncthreads();
+    const int j = j0 + threadIdx.x;
+    if (j >= a.W) return;
+    float* out = a.out + (size_t)row * COUT * a.W + j;
+    const float* x = tile + threadIdx.x;
+    if (CIN == 1) {
+        float xv[KT];
+#pragma unroll
+        for (int t = 0; t < KT; ++t) xv[t] = x[t];
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) {
+            float acc = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < KT; ++t) acc = fmaf(conv_weight(a, co, 0, t), xv[t], acc);
+            float* o = out + (size_t)co * a.W;
+            if (a.accumulate) acc += *o;
+            if (a.relu) acc = fmaxf(acc, 0.0f);
+            *o = acc;
+        }
+    } else {
+        float acc = a.bias ? a.bias[0] : 0.0f;
+#pragma unroll
+        for (int ci = 0; ci < CIN; ++ci)
+#pragma unroll
+            for (int t = 0; t < KT; ++t) acc = fmaf(conv_weight(a, 0, ci, t), x[ci * kSpan + t], acc);
+        if (a.accumulate) acc += *out;
+        if (a.relu) acc = fmaxf(acc, 0.0f);
+        *out = acc;
+    }
+}
+
 hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s)
 {
+    if (a.K == 9 && ((a.cin == 1 && a.cout == 32) || (a.cin == 32 && a.cout == 1))) {
+        dim3 grid((a.W + 255) / 256, a.rows);
+        if (a.cin == 1)
+            hipLaunchKernelGGL((conv_narrow_kernel<1, 32, 9>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((conv_narrow_kernel<32, 1, 9>), grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     if (mfma_shape(a.cin, a.cout, a.K)) {
         using C = ConvMfma<32, 32, 9>;
         const int cpr = (a.W + C::kChunk - 1) / C::kChunk;
@@ -367,6 +426,20 @@ hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s)
 // ---------------------------------------------------------------------------
 // weight and bias gradients
 // ---------------------------------------------------------------------------
+// sum_p d[p] x[p] in FP64 with eight independent partial sums (the chains
+// of dependent FMAs would otherwise bound the loop by their latency)
+__device__ __forceinline__ double dot_f64(const float* d, const float* x, int n)
+{
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int p = 0;
+    for (; p + 8 <= n; p += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] = fma((double)d[p + u], (double)x[p + u], s[u]);
+    }
+    for (; p < n; ++p) s[0] = fma((double)d[p], (double)x[p], s[0]);
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // Block b sums over rows b, b + B, b + 2B, ... into
 //   part[b][(co*cin + ci)*K + t]  and  part_bias[b][co]
 // in FP64; thread e owns entries e, e + 256, ...  For each row the block
@@ -410,11 +483,7 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(LearnGradArgs a)
                     const int t = e % a.K;
                     const int ci = (e / a.K) % a.cin;
                     const int co = e / (a.K * a.cin);
-                    const float* d = dy + co * kGradChunk;
-                    const float* xx = x + ci * span + t;
-                    double s = 0.0;
-                    for (int p = 0; p < n; ++p) s = fma((double)d[p], (double)xx[p], s);
-                    acc[q] += s;
+                    acc[q] += dot_f64(dy + co * kGradChunk, x + ci * span + t, n);
                 }
             }
             if (threadIdx.x < a.cout) {
@@ -492,11 +561,7 @@ __global__ __launch_bounds__(256) void wgrad_long_partial_kernel(LearnGradArgs a
 #pragma unroll
         for (int q = 0; q < kLongPer; ++q) {
             const int t = threadIdx.x + 256 * q;
-            if (t < a.K) {
-                double s = 0.0;
-                for (int p = 0; p < a.W; ++p) s = fma((double)dy[p], (double)x[p + t], s);
-                acc[q] += s;
-            }
+            if (t < a.K) acc[q] += dot_f64(dy, x + t, a.W);
         }
         if (threadIdx.x == 0) {
             double s = 0.0;
