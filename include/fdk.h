@@ -226,7 +226,9 @@ int fdk_update_probe(float* a, size_t n, float s, void* stream);
 int fdk_profile_begin(void);
 int fdk_profile_end(double* kernel_ms, int* launches);
 
-/* Views per backprojection launch (1..64, default 64); 0 reads it back. */
+/* Views per launch of the fused backprojection and the forward projection
+   (1..1024, default 64; the staging buffer holds that many views, up to
+   8 GiB); 0 reads it back.  The plain kernel takes at most 64 per launch. */
 int fdk_set_batch(int views_per_pass);
 
 /*

@@ -43,10 +43,17 @@ struct Staging {
     void* ptr = nullptr;
     size_t bytes = 0;
     hipEvent_t last_use = nullptr;  // recorded after the last call's kernels
+    // the folded matrices of a call: written on the host into pinned
+    // memory, copied once to the end of the staging buffer
+    float* host_mats = nullptr;
+    size_t host_floats = 0;
+    hipEvent_t mats_copied = nullptr;  // recorded after the last such copy
 };
 std::mutex g_stage_mu;
 std::unordered_map<int, Staging> g_stage;
-std::atomic<int> g_batch{kMaxBatch};
+// views per pass of the fused paths (fdk_set_batch); 64 measured best on fdk512
+constexpr int kDefaultBatch = 64;
+std::atomic<int> g_batch{kDefaultBatch};
 
 // Staged layout of the fused path (tuning knob; FDK_LAYOUT=rows|pairs|quads|
 // dpairs|dquads in the environment overrides the default at load time).
@@ -68,7 +75,7 @@ int g_fp_lds = []() {
     const char* e = std::getenv("FDK_FP_LDS");
     return (e && !std::strcmp(e, "0")) ? 0 : 1;
 }();
-constexpr size_t kMaxStagingBytes = size_t(4) << 30;
+constexpr size_t kMaxStagingBytes = size_t(8) << 30;
 
 // ---- kernel timing (per calling thread) ----------------------------------
 struct Timing {
@@ -225,7 +232,7 @@ int acquire_staging(size_t bytes, hipStream_t stream, Staging** out)
 
 // Launch geometry shared by the backprojection and the forward projection:
 // everything in FusedArgs except the staged planes and the matrices.
-void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long long plane)
+void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long long plane, int zdepth)
 {
     const int ku = (W - 1) / 2, kv = (H - 1) / 2;
     A.vol = volume;
@@ -250,16 +257,16 @@ void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long l
     A.c = 0.5f * (float)(N - 1);
     A.tiles_x = (N + kTileX - 1) / kTileX;
     A.tiles_y = (N + kTileY - 1) / kTileY;
-    A.zchunks = (N + kFusedZ - 1) / kFusedZ;
+    A.zchunks = (N + zdepth - 1) / zdepth;
     const long long blocks = (long long)A.tiles_x * A.tiles_y * A.zchunks;
     A.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
 }
 
-// Fold the matrices of views [v0, v0+cnt) into A.m; returns whether some
-// voxel may have w <= 0, and sets the workgroup order from the batch's mean
-// ray direction.
-bool fold_batch(FusedArgs& A, const double* P, const float* view_scale, int v0, int cnt, int N,
-                float voxel_size, const float* origin, int H, int W)
+// Fold the matrices of views [v0, v0+cnt) into out (cnt x 12 floats);
+// returns whether some voxel may have w <= 0, and sets the workgroup order
+// from the batch's mean ray direction.
+bool fold_batch(FusedArgs& A, float* out, const double* P, const float* view_scale, int v0,
+                int cnt, int N, float voxel_size, const float* origin, int H, int W)
 {
     const int ku = (W - 1) / 2, kv = (H - 1) / 2;
     const double c = 0.5 * (N - 1);
@@ -272,13 +279,71 @@ bool fold_batch(FusedArgs& A, const double* P, const float* view_scale, int v0, 
         double Q[12];
         fold_matrix(P + 12 * (size_t)(v0 + j), N, voxel_size, origin, ku, kv, lambda, Q);
         wcheck |= needs_wcheck(Q, c);
-        for (int k = 0; k < 12; ++k) A.m[j][k] = (float)Q[k];
+        for (int k = 0; k < 12; ++k) out[12 * (size_t)j + k] = (float)Q[k];
         double d[3];
         source_direction(Q, d);
         for (int k = 0; k < 3; ++k) ray[k] += std::fabs(d[k]);
     }
     A.y_fastest = ray[1] > ray[0] ? 1 : 0;
     return wcheck;
+}
+
+// Per-batch launch parameters of a call, with every view's folded matrix
+// copied to the device (at `dev`, inside the staging buffer, so the
+// staging buffer's ordering protects it).
+struct Batches {
+    std::vector<int> v0, count, wcheck, y_fastest;
+};
+
+int fold_and_upload(Staging* st, float* dev, const double* P, const float* view_scale,
+                    int n_views, int batch, int N, float voxel_size, const float* origin, int H,
+                    int W, hipStream_t stream, Batches* B)
+{
+    hipError_t e;
+    const size_t floats = 12 * (size_t)n_views;
+    if (!st->mats_copied) {
+        e = hipEventCreateWithFlags(&st->mats_copied, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    } else {
+        // the previous call's copy must have read the pinned buffer
+        e = hipEventSynchronize(st->mats_copied);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    if (st->host_floats < floats) {
+        if (st->host_mats) {
+            e = hipHostFree(st->host_mats);
+            st->host_mats = nullptr;
+            st->host_floats = 0;
+            if (e != hipSuccess) return hip_fail(e, "hipHostFree");
+        }
+        e = hipHostMalloc((void**)&st->host_mats, floats * sizeof(float), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            st->host_mats = nullptr;
+            return hip_fail(e, "hipHostMalloc");
+        }
+        st->host_floats = floats;
+    }
+    FusedArgs A = {};
+    for (int v0 = 0; v0 < n_views; v0 += batch) {
+        const int cnt = std::min(batch, n_views - v0);
+        const bool wcheck = fold_batch(A, st->host_mats + 12 * (size_t)v0, P, view_scale, v0,
+                                       cnt, N, voxel_size, origin, H, W);
+        B->v0.push_back(v0);
+        B->count.push_back(cnt);
+        B->wcheck.push_back(wcheck ? 1 : 0);
+        B->y_fastest.push_back(A.y_fastest);
+    }
+    e = hipMemcpyAsync(dev, st->host_mats, floats * sizeof(float), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "matrix copy");
+    e = hipEventRecord(st->mats_copied, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return FDK_OK;
+}
+
+// bytes of `n` views' planes rounded up for the matrices that follow them
+size_t planes_region(size_t n, size_t plane_bytes)
+{
+    return (n * plane_bytes + 255) & ~size_t(255);
 }
 
 int run_fused(float* volume, int N, float voxel_size, const float* origin, const void* proj,
@@ -299,16 +364,22 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     batch = std::min(batch, n_views);
 
     FusedArgs A = {};
-    setup_args(A, volume, N, H, W, Wp, (long long)Hp * Wp);
+    setup_args(A, volume, N, H, W, Wp, (long long)Hp * Wp, fused_z(dtype));
 
     std::lock_guard<std::mutex> lock(g_stage_mu);
     Staging* st = nullptr;
-    int rc = acquire_staging((size_t)batch * plane_bytes, stream, &st);
+    const size_t planes = planes_region(batch, plane_bytes);
+    int rc = acquire_staging(planes + 48 * (size_t)n_views, stream, &st);
     if (rc != FDK_OK) return rc;
     A.img = st->ptr;
+    float* mats = (float*)((char*)st->ptr + planes);
+    Batches B;
+    rc = fold_and_upload(st, mats, P, view_scale, n_views, batch, N, voxel_size, origin, H, W,
+                         stream, &B);
+    if (rc != FDK_OK) return rc;
 
-    for (int v0 = 0; v0 < n_views; v0 += batch) {
-        const int cnt = std::min(batch, n_views - v0);
+    for (size_t b = 0; b < B.v0.size(); ++b) {
+        const int v0 = B.v0[b], cnt = B.count[b];
         StageArgs S;
         S.src = (const char*)proj + (size_t)v0 * H * W * esz;
         S.dst = st->ptr;
@@ -320,10 +391,12 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
         S.layout = layout;
         hipError_t e = launch_stage(S, dtype, stream);
         if (e != hipSuccess) return hip_fail(e, "stage launch");
-        const bool wcheck = fold_batch(A, P, view_scale, v0, cnt, N, voxel_size, origin, H, W);
+        A.count = cnt;
+        A.m = mats + 12 * (size_t)v0;
+        A.y_fastest = B.y_fastest[b];
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
-        e = launch_fused(A, dtype, layout, wcheck, stream);
+        e = launch_fused(A, dtype, layout, B.wcheck[b] != 0, stream);
         if (e != hipSuccess) return hip_fail(e, "backprojection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
     }
@@ -346,30 +419,39 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
     batch = std::min(batch, n_views);
 
     FusedArgs A = {};
-    setup_args(A, const_cast<float*>(volume), N, H, W, Wp, (long long)Hp * Wp);
+    setup_args(A, const_cast<float*>(volume), N, H, W, Wp, (long long)Hp * Wp, kFpZ);
 
     std::lock_guard<std::mutex> lock(g_stage_mu);
     Staging* st = nullptr;
-    int rc = acquire_staging((size_t)batch * plane_bytes, stream, &st);
+    const size_t planes = planes_region(batch, plane_bytes);
+    int rc = acquire_staging(planes + 48 * (size_t)n_views, stream, &st);
     if (rc != FDK_OK) return rc;
     A.img = st->ptr;
+    float* mats = (float*)((char*)st->ptr + planes);
+    Batches B;
+    rc = fold_and_upload(st, mats, P, nullptr, n_views, batch, N, voxel_size, origin, H, W,
+                         stream, &B);
+    if (rc != FDK_OK) return rc;
 
-    for (int v0 = 0; v0 < n_views; v0 += batch) {
-        const int cnt = std::min(batch, n_views - v0);
+    for (size_t b = 0; b < B.v0.size(); ++b) {
+        const int v0 = B.v0[b], cnt = B.count[b];
         hipError_t e = launch_zero((float*)st->ptr, (size_t)cnt * Hp * Wp, stream);
         if (e != hipSuccess) return hip_fail(e, "zero launch");
-        const bool wcheck = fold_batch(A, P, nullptr, v0, cnt, N, voxel_size, origin, H, W);
+        A.count = cnt;
+        A.m = mats + 12 * (size_t)v0;
+        A.y_fastest = B.y_fastest[b];
+        const bool wcheck = B.wcheck[b] != 0;
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
         if (wcheck || !g_fp_lds) {
             e = launch_scatter(A, wcheck, stream);
         } else {
-            FusedArgs B = A;  // 16 x 16 column tiles
-            B.tiles_x = (N + 15) / 16;
-            B.tiles_y = (N + 15) / 16;
-            const long long blocks = (long long)B.tiles_x * B.tiles_y * B.zchunks;
-            B.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
-            e = launch_scatter_lds(B, stream);
+            FusedArgs C = A;  // 16 x 16 column tiles
+            C.tiles_x = (N + 15) / 16;
+            C.tiles_y = (N + 15) / 16;
+            const long long blocks = (long long)C.tiles_x * C.tiles_y * C.zchunks;
+            C.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+            e = launch_scatter_lds(C, stream);
         }
         if (e != hipSuccess) return hip_fail(e, "forward projection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
@@ -401,7 +483,7 @@ int run_plain(float* volume, int N, float voxel_size, const float* origin, const
     A.oy = origin[1];
     A.oz = origin[2];
     A.vs = voxel_size;
-    const int batch = std::min(g_batch.load(), n_views);
+    const int batch = std::min(std::min(g_batch.load(), kPlainBatch), n_views);
     for (int v0 = 0; v0 < n_views; v0 += batch) {
         const int cnt = std::min(batch, n_views - v0);
         A.proj = proj + (size_t)v0 * H * W;
@@ -746,6 +828,15 @@ int fdk_release(void)
         if (st.ptr) {
             hipError_t e = hipFree(st.ptr);
             if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "hipFree(staging)");
+        }
+        if (st.mats_copied) {
+            hipError_t e = hipEventSynchronize(st.mats_copied);
+            if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "hipEventSynchronize");
+            (void)hipEventDestroy(st.mats_copied);
+        }
+        if (st.host_mats) {
+            hipError_t e = hipHostFree(st.host_mats);
+            if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "hipHostFree");
         }
     }
     g_stage.clear();

@@ -1,8 +1,8 @@
 // Backprojection kernels for gfx950 (CDNA4).
 //
 // fused: the optimised kernel.  One thread owns an (x, y) voxel column and
-//   kFusedZ consecutive z voxels; the views of a batch are fused in one
-//   pass with the kFusedZ voxel sums held in registers, so the volume is
+//   fused_z consecutive z voxels; the views of a batch are fused in one
+//   pass with the fused_z voxel sums held in registers, so the volume is
 //   read and written once per batch (the image-loop blocking of the paper's
 //   Section 6.2, with registers in place of the L1-resident voxel line).
 //   Per (voxel, view) the work is the paper's three parts (Section 3.2):
@@ -30,9 +30,9 @@ namespace fdk {
 // ---------------------------------------------------------------------------
 // storage types
 // ---------------------------------------------------------------------------
-struct TF32 { using elem = float; };
-struct TF16 { using elem = uint16_t; };
-struct TBF16 { using elem = uint16_t; };
+struct TF32 { using elem = float; static constexpr int id = kF32; };
+struct TF16 { using elem = uint16_t; static constexpr int id = kF16; };
+struct TBF16 { using elem = uint16_t; static constexpr int id = kBF16; };
 
 // ---------------------------------------------------------------------------
 // stage
@@ -251,15 +251,16 @@ __device__ __forceinline__ float bilerp16(TBF16, uint2 q, float au, float av)
 constexpr int kGroup = FDK_GROUP;
 static_assert(kWaveX * kWaveY == 64, "a wave covers 64 columns");
 
-// One view's contribution to the kFusedZ voxels of this thread.  CLAMP
+// One view's contribution to the fused_z voxels of this thread.  CLAMP
 // selects the clamped tap addressing (needed when some voxel of the wave
 // may project outside the zero border of the staged plane).
 template <typename TT, int LAYOUT, bool WCHECK, bool CLAMP>
-__device__ __forceinline__ void accumulate_view(const FusedArgs& A, const float* m, float xp,
+__device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_float* m, float xp,
                                                 float yp, float zp0,
                                                 __amdgpu_buffer_rsrc_t rsrc,
-                                                float (&acc)[kFusedZ])
+                                                float (&acc)[fused_z(TT::id)])
 {
+    constexpr int kFusedZ = fused_z(TT::id);
     using E = typename TT::elem;
     constexpr bool kIsF32 = sizeof(E) == 4;
     constexpr uint32_t kElem = sizeof(E) * layout_width(LAYOUT);
@@ -330,6 +331,7 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
 {
     using E = typename TT::elem;
     constexpr uint32_t kElem = sizeof(E) * layout_width(LAYOUT);
+    constexpr int kFusedZ = fused_z(TT::id);
     int bid = blockIdx.x;
     if (A.xcd_remap) {
         const int per = gridDim.x >> 3;
@@ -373,8 +375,9 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
 
     const uint32_t plane_bytes = (uint32_t)(A.plane * (long long)kElem);
     const char* plane = (const char*)A.img;
+    const const_float* mats = as_constant(A.m);
     for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const float* m = A.m[j];
+        const const_float* m = mats + 12 * j;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
         if constexpr (WCHECK) {
             accumulate_view<TT, LAYOUT, WCHECK, true>(A, m, xp, yp, zp0, rsrc, acc);

@@ -6,10 +6,12 @@
 
 namespace fdk {
 
-// Views per backprojection launch; their matrices travel in the kernel
-// arguments (12 floats each), which keeps every call free of host-to-device
-// copies and under the 4 KiB kernel-argument limit.
-constexpr int kMaxBatch = 64;
+// Views per launch of the fused backprojection and the forward projection
+// (their folded matrices go to device memory once per call, 48 bytes per
+// view), and of the plain kernel (matrices in the kernel arguments, under
+// the 4 KiB kernel-argument limit).
+constexpr int kMaxBatch = 1024;
+constexpr int kPlainBatch = 64;
 
 // Zero border of a staged projection plane (pixels on every side).  Taps
 // are clamped into [-2, W] x [-2, H], so a 2-pixel border is enough for
@@ -63,7 +65,7 @@ struct FusedArgs {
     int tiles_x, tiles_y, zchunks;
     int xcd_remap;       // 1: spread consecutive tiles over XCD-local ranges
     int y_fastest;       // 1: consecutive workgroups step along y, else along x
-    float m[kMaxBatch][12];
+    const float* m;      // count x 12 folded matrices of this batch (device memory)
 };
 
 // Arguments of the plain kernel: world-coordinate matrices (FP32 roundings
@@ -74,7 +76,7 @@ struct PlainArgs {
     int N, H, W;
     float ox, oy, oz, vs;
     int count;
-    float m[kMaxBatch][12];
+    float m[kPlainBatch][12];
 };
 
 struct StageArgs {
@@ -149,10 +151,11 @@ hipError_t launch_mse(float* grad, float* loss, double* part, int nparts, const 
 constexpr int kGradBlocks = 1024;  // partial-sum blocks of the weight gradients
 constexpr int kMseParts = 1024;
 
-#ifndef FDK_FUSED_Z
-#define FDK_FUSED_Z 16
-#endif
-constexpr int kFusedZ = FDK_FUSED_Z;  // z voxels per thread in the fused kernel
+// z voxels per thread: the forward projection kernels, and the fused
+// backprojection by storage type (FP32 taps: 16; 16-bit taps: 8, whose
+// smaller wave boxes clip more finely; both measured best on fdk512)
+constexpr int kFpZ = 16;
+__host__ __device__ constexpr int fused_z(int storage) { return storage == kF32 ? 16 : 8; }
 // A wave covers kWaveX x kWaveY voxel columns; a workgroup stacks kWgWaves
 // waves along y.
 #ifndef FDK_WG_WAVES

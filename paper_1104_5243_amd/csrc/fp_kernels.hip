@@ -34,22 +34,22 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
     const int wy0 = ty * kTileY + wave * kWaveY;
     const int x = wx0 + (lane % kWaveX);
     const int y = wy0 + (lane / kWaveX);
-    const int zl0 = zc * kFusedZ;
+    const int zl0 = zc * kFpZ;
     const float xp = (float)x - A.c;
     const float yp = (float)y - A.c;
     const float zp0 = (float)(A.z_first + zl0) - A.c;
     const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
     const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
-    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
+    const float czp = zp0 + ((lane & 4) ? (float)(kFpZ - 1) : 0.0f);
     const bool corner_lane = lane < 8;
 
     // the thread's voxel values (0 outside the volume)
-    float val[kFusedZ];
+    float val[kFpZ];
     const bool inside = x < A.N && y < A.N;
     const size_t slice = (size_t)A.N * A.N;
     const float* src = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
 #pragma unroll
-    for (int i = 0; i < kFusedZ; ++i)
+    for (int i = 0; i < kFpZ; ++i)
         val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
 
     const int Wp = A.Wp;
@@ -57,8 +57,9 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
     const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
     const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
     const char* plane = (const char*)A.img;
+    const const_float* mats = as_constant(A.m);
     for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const float* m = A.m[j];
+        const const_float* m = mats + 12 * j;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
         if constexpr (!WCHECK) {
             const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
         const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
         const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
 #pragma unroll
-        for (int i = 0; i < kFusedZ; ++i) {
+        for (int i = 0; i < kFpZ; ++i) {
             const float zp = zp0 + (float)i;
             const float uw = fmaf(zp, m[2], bu);
             const float vw = fmaf(zp, m[6], bv);
@@ -140,22 +141,22 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
     const int bx0 = tx * kFpTile, by0 = ty * kFpTile;
     const int x = bx0 + (threadIdx.x % kFpTile);
     const int y = by0 + (threadIdx.x / kFpTile);
-    const int zl0 = zc * kFusedZ;
+    const int zl0 = zc * kFpZ;
     const float xp = (float)x - A.c;
     const float yp = (float)y - A.c;
     const float zp0 = (float)(A.z_first + zl0) - A.c;
     // lanes 0..7 of every wave hold the corners of the workgroup's box
     const float cxp = (float)(bx0 + ((lane & 1) ? kFpTile - 1 : 0)) - A.c;
     const float cyp = (float)(by0 + ((lane & 2) ? kFpTile - 1 : 0)) - A.c;
-    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
+    const float czp = zp0 + ((lane & 4) ? (float)(kFpZ - 1) : 0.0f);
     const bool corner_lane = lane < 8;
 
-    float val[kFusedZ];
+    float val[kFpZ];
     const bool inside = x < A.N && y < A.N;
     const size_t slice = (size_t)A.N * A.N;
     const float* src = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
 #pragma unroll
-    for (int i = 0; i < kFusedZ; ++i)
+    for (int i = 0; i < kFpZ; ++i)
         val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
 
     const int Wp = A.Wp;
@@ -165,8 +166,9 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
     const int lo_u = (int)A.lo_u, hi_u = (int)(A.hi_u - 0.5f);
     const int lo_v = (int)A.lo_v, hi_v = (int)(A.hi_v - 0.5f);
     const char* plane = (const char*)A.img;
+    const const_float* mats = as_constant(A.m);
     for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const float* m = A.m[j];
+        const const_float* m = mats + 12 * j;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
         const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
         const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
         const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
         const int last = TW * TH - TW - 2;
 #pragma unroll
-        for (int i = 0; i < kFusedZ; ++i) {
+        for (int i = 0; i < kFpZ; ++i) {
             const float zp = zp0 + (float)i;
             const float uw = fmaf(zp, m[2], bu);
             const float vw = fmaf(zp, m[6], bv);

@@ -33,4 +33,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
                                              0x00020000);
 }
 
+// Read-only data that every lane reads at the same address (the folded
+// matrices of a batch), seen through the constant address space so that the
+// compiler reads it with scalar loads into SGPRs, as it does kernel
+// arguments.  The data must not change while the kernel runs.
+typedef __attribute__((address_space(4))) const float const_float;
+__device__ __forceinline__ const const_float* as_constant(const float* p)
+{
+    return (const const_float*)p;
+}
+
 }  // namespace fdk

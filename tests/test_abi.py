@@ -95,8 +95,10 @@ def test_zero_views_is_a_noop_without_pointers():
 def test_batch_setting():
     L = fdk.lib()
     old = L.fdk_set_batch(0)
-    assert 1 <= old <= 64
-    assert L.fdk_set_batch(65) == fdk.FDK_ERR_INVALID_ARG
+    assert 1 <= old <= 1024
+    assert L.fdk_set_batch(1025) == fdk.FDK_ERR_INVALID_ARG
+    assert L.fdk_set_batch(-1) == fdk.FDK_ERR_INVALID_ARG
+    assert L.fdk_set_batch(496) == 496
     assert L.fdk_set_batch(7) == 7
     assert L.fdk_set_batch(old) == old
 
