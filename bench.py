@@ -172,8 +172,14 @@ def bench_prefilter(args, torch, fdk, synth, dev):
 
     t, kms, launches = _timed(torch, fdk, step, args.warmup, args.steps)
     rows = V * H
-    # per output: the centre tap and (W/2 odd taps) x (one add + one FMA)
-    flop = rows * W * (1 + 3 * (W // 2))
+    # FFT convolution of two rows per complex transform of length L (radix 4,
+    # 34 flop per butterfly; radix 2, 10 flop), forward and inverse, and the
+    # spectrum product (6 flop per point)
+    L, lg = 4, 2
+    while L < 2 * W - 1:
+        L, lg = 2 * L, lg + 1
+    per_transform = (lg // 2) * (L // 4) * 34 + (lg % 2) * (L // 2) * 10
+    flop = (rows + 1) // 2 * (2 * per_transform + 6 * L)
     ks = kms / 1e3
     ach = flop * args.steps / ks / 1e12
     log(f"prefilter: {t * 1e3:.2f} ms/step, {ach:.2f} TFLOP/s FP64")
@@ -191,7 +197,8 @@ def bench_prefilter(args, torch, fdk, synth, dev):
         "Mrow/s", t, "f64",
         f"fdk512 pre-filter: {V} line-integral views of {W}x{H}, FP32 in/out, FP64 inside",
         {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
-         "frac": round(ach / 78.6, 4), "traffic": None, "kernel": "prefilter_kernel",
+         "frac": round(ach / 78.6, 4), "traffic": None,
+         "kernel": f"fft_conv_kernel (FP64 FFT, L={L}, two rows per transform)",
          "launches_per_step": launches // args.steps,
          "kernel_ms_per_step": round(kms / args.steps, 3)},
         None if tc is None else

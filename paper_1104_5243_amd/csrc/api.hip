@@ -558,14 +558,45 @@ int fdk_forward_project(float* proj_stack, int n_views, int H, int W, const doub
                        (hipStream_t)stream);
 }
 
+// FFT row convolution: transform length, tables in the staging buffer
+// (ordered after its previous user), the three launches, timed as one.
+int run_fft_conv(FftConvArgs A, hipStream_t stream)
+{
+    int L = 4, log2L = 2;
+    while (L < 2 * A.W - 1) {
+        L <<= 1;
+        ++log2L;
+    }
+    A.L = L;
+    A.log2L = log2L;
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    Staging* st = nullptr;
+    const size_t tables = A.weighted ? ((size_t)A.views + A.H) * A.W * sizeof(double) : 0;
+    int rc = acquire_staging((size_t)(kFftMax + L) * 16 + tables, stream, &st);
+    if (rc != FDK_OK) return rc;
+    A.tw = (double2*)st->ptr;
+    A.spectrum = A.tw + kFftMax;
+    A.parker = (double*)(A.spectrum + L);
+    A.cosw = A.parker + (size_t)A.views * A.W;
+    hipEvent_t t0;
+    if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
+    hipError_t e = launch_fft_conv(A, stream);
+    if (e != hipSuccess) return hip_fail(e, "FFT convolution launch");
+    if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
+    e = hipEventRecord(st->last_use, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return FDK_OK;
+}
+
 int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double beta0,
                   double dbeta, double delta, double sid, double sdd, double pixel,
                   void* stream)
 {
     g_err.clear();
     if (n_views < 0) return fail(FDK_ERR_INVALID_ARG, "n_views=%d < 0", n_views);
-    if (H < 1 || W < 1 || W > 2000 || H > 32768)
-        return fail(FDK_ERR_INVALID_ARG, "detector %dx%d outside [1, 2000] x [1, 32768]", W, H);
+    if (H < 1 || W < 1 || W > kFftMax / 2 || H > 32768)
+        return fail(FDK_ERR_INVALID_ARG, "detector %dx%d outside [1, %d] x [1, 32768]", W, H,
+                    kFftMax / 2);
     if (n_views == 0) return FDK_OK;
     if (!out || !in) return fail(FDK_ERR_INVALID_ARG, "out or in is NULL");
     if (out == in) return fail(FDK_ERR_INVALID_ARG, "out and in must be distinct buffers");
@@ -576,25 +607,22 @@ int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double
         return fail(FDK_ERR_INVALID_ARG, "sid, sdd and pixel must be finite and > 0");
     if ((long long)n_views * H > 0x7fffffffLL)
         return fail(FDK_ERR_INVALID_ARG, "too many rows");
-    PrefilterArgs A;
+    FftConvArgs A = {};
     A.out = out;
     A.in = in;
     A.rows = n_views * H;
-    A.H = H;
     A.W = W;
+    A.H = H;
+    A.tau = pixel * sid / sdd;
+    A.scale = A.tau * dbeta;
+    A.weighted = 1;
+    A.views = n_views;
     A.beta0 = beta0;
     A.dbeta = dbeta;
     A.delta = delta;
     A.sdd = sdd;
     A.pixel = pixel;
-    A.tau = pixel * sid / sdd;
-    A.scale = pixel * sid / sdd * dbeta;
-    hipEvent_t t0;
-    int rc = timed_begin((hipStream_t)stream, &t0);
-    if (rc != FDK_OK) return rc;
-    hipError_t e = launch_prefilter(A, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "prefilter launch");
-    return timed_end((hipStream_t)stream, t0);
+    return run_fft_conv(A, (hipStream_t)stream);
 }
 
 int fdk_conv_rows(float* out, const float* in, const float* weight, const float* bias, int rows,
@@ -615,6 +643,24 @@ int fdk_conv_rows(float* out, const float* in, const float* weight, const float*
     if (!out || !in || !weight) return fail(FDK_ERR_INVALID_ARG, "out, in or weight is NULL");
     if (out == in) return fail(FDK_ERR_INVALID_ARG, "out and in must be distinct");
     if (rows > 65535) return fail(FDK_ERR_UNSUPPORTED, "rows=%d > 65535 per call", rows);
+    if (cin == 1 && cout == 1 && K > 32 && K == 2 * W - 1 && pad == W - 1 && W <= kFftMax / 2) {
+        // a full-row ramp: FFT convolution in FP64
+        FftConvArgs F = {};
+        F.out = out;
+        F.in = in;
+        F.rows = rows;
+        F.W = W;
+        F.H = 1;
+        F.taps = weight;
+        F.K = K;
+        F.pad = pad;
+        F.transpose = (flags & FDK_CONV_TRANSPOSE) ? 1 : 0;
+        F.scale = 1.0;
+        F.bias = bias;
+        F.relu = (flags & FDK_CONV_RELU) ? 1 : 0;
+        F.accumulate = (flags & FDK_CONV_ACCUMULATE) ? 1 : 0;
+        return run_fft_conv(F, (hipStream_t)stream);
+    }
     LearnConvArgs A;
     A.out = out;
     A.in = in;

@@ -95,14 +95,32 @@ struct UnstageArgs {
     int count;
 };
 
-struct PrefilterArgs {
+
+// FFT row convolution (fft_kernels.hip).
+constexpr int kFftMax = 4096;  // largest transform: rows of up to 2048 samples
+struct FftConvArgs {
     float* out;
     const float* in;
-    int rows, H, W;      // rows = n_views * H
-    double beta0, dbeta;
-    double delta, sdd, pixel, tau;
-    double scale;        // tau * dbeta
+    int rows, W, H;       // H: detector rows per view (weighted input only)
+    int L, log2L;         // transform length, a power of 2 >= max(4, 2W - 1)
+    double2* spectrum;    // L entries, written by the spectrum kernel
+    double2* tw;          // kFftMax twiddles, written by the twiddle kernel
+    // taps h[n], -(W-1) <= n <= W-1: Ram-Lak at spacing tau if taps is null,
+    // else h[n] = taps[pad - n] (reversed if transpose); all scaled by scale
+    const float* taps;
+    int K, pad, transpose;
+    double tau, scale;
+    // Feldkamp weights of the input (weighted = 1): cosine and Parker, with
+    // their tables (views x W and H x W, written by the weights kernel)
+    int weighted, views;
+    double beta0, dbeta, delta, sdd, pixel;
+    double* parker;
+    double* cosw;
+    // output: + bias[0] (if not null), + out (accumulate), ReLU
+    const float* bias;
+    int accumulate, relu;
 };
+hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s);
 
 struct LearnConvArgs {
     float* out;
@@ -133,7 +151,6 @@ hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s);
 // as launch_scatter for w > 0 everywhere; tiles of 16 x 16 columns
 hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s);
 hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s);
-hipError_t launch_prefilter(const PrefilterArgs& a, hipStream_t s);
 hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s);
 hipError_t launch_wgrad(const LearnGradArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_wgrad_long(const LearnGradArgs& a, int nblocks, hipStream_t s);
