@@ -22,7 +22,15 @@
 
 namespace fdk {
 
-constexpr int kFftThreads = 256;
+// 16 waves per workgroup: a stage is one radix-4 butterfly per thread at L =
+// 4096, and the waves hide each other's LDS latency (256 threads: 16.8 ms,
+// 512: 14.6 ms, 1024: 13.4 ms for fdk512's pre-filter)
+constexpr int kFftThreads = 1024;
+
+// LDS position of element p: one pad element after every 8, so that the
+// power-of-two strides of the butterflies spread over the banks.
+__device__ __forceinline__ int px(int p) { return p + (p >> 3); }
+constexpr int kFftLds = kFftMax + kFftMax / 8;  // double2 elements (72 KiB)
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return {a.x - b.x, a.y - b.y}; }
@@ -48,21 +56,21 @@ __device__ __forceinline__ void dif_stage(double2* x, int L, int Ns, const doubl
         const int j = b & (s - 1);
         const int base = (b - j) * R + j;
         if (R == 2) {
-            const double2 a0 = x[base], a1 = x[base + s];
-            x[base] = cadd(a0, a1);
-            x[base + s] = cmul(csub(a0, a1), tw[j * ts]);
+            const double2 a0 = x[px(base)], a1 = x[px(base + s)];
+            x[px(base)] = cadd(a0, a1);
+            x[px(base + s)] = cmul(csub(a0, a1), tw[j * ts]);
         } else {
-            const double2 a0 = x[base], a1 = x[base + s], a2 = x[base + 2 * s],
-                          a3 = x[base + 3 * s];
+            const double2 a0 = x[px(base)], a1 = x[px(base + s)], a2 = x[px(base + 2 * s)],
+                          a3 = x[px(base + 3 * s)];
             const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3),
                           t3 = csub(a1, a3);
             // (-i) t3 = (t3.y, -t3.x)
             const double2 y1 = {t1.x + t3.y, t1.y - t3.x};
             const double2 y3 = {t1.x - t3.y, t1.y + t3.x};
-            x[base] = cadd(t0, t2);
-            x[base + s] = cmul(y1, tw[j * ts]);
-            x[base + 2 * s] = cmul(csub(t0, t2), tw[2 * j * ts]);
-            x[base + 3 * s] = cmul(y3, tw[3 * j * ts]);
+            x[px(base)] = cadd(t0, t2);
+            x[px(base + s)] = cmul(y1, tw[j * ts]);
+            x[px(base + 2 * s)] = cmul(csub(t0, t2), tw[2 * j * ts]);
+            x[px(base + 3 * s)] = cmul(y3, tw[3 * j * ts]);
         }
     }
 }
@@ -78,21 +86,21 @@ __device__ __forceinline__ void dit_stage(double2* x, int L, int Ns, const doubl
         const int j = b & (s - 1);
         const int base = (b - j) * R + j;
         if (R == 2) {
-            const double2 a0 = x[base], a1 = cmulc(x[base + s], tw[j * ts]);
-            x[base] = cadd(a0, a1);
-            x[base + s] = csub(a0, a1);
+            const double2 a0 = x[px(base)], a1 = cmulc(x[px(base + s)], tw[j * ts]);
+            x[px(base)] = cadd(a0, a1);
+            x[px(base + s)] = csub(a0, a1);
         } else {
-            const double2 a0 = x[base];
-            const double2 a1 = cmulc(x[base + s], tw[j * ts]);
-            const double2 a2 = cmulc(x[base + 2 * s], tw[2 * j * ts]);
-            const double2 a3 = cmulc(x[base + 3 * s], tw[3 * j * ts]);
+            const double2 a0 = x[px(base)];
+            const double2 a1 = cmulc(x[px(base + s)], tw[j * ts]);
+            const double2 a2 = cmulc(x[px(base + 2 * s)], tw[2 * j * ts]);
+            const double2 a3 = cmulc(x[px(base + 3 * s)], tw[3 * j * ts]);
             const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3),
                           t3 = csub(a1, a3);
             // (+i) t3 = (-t3.y, t3.x)
-            x[base] = cadd(t0, t2);
-            x[base + s] = {t1.x - t3.y, t1.y + t3.x};
-            x[base + 2 * s] = csub(t0, t2);
-            x[base + 3 * s] = {t1.x + t3.y, t1.y - t3.x};
+            x[px(base)] = cadd(t0, t2);
+            x[px(base + s)] = {t1.x - t3.y, t1.y + t3.x};
+            x[px(base + 2 * s)] = csub(t0, t2);
+            x[px(base + 3 * s)] = {t1.x + t3.y, t1.y - t3.x};
         }
     }
 }
@@ -145,10 +153,10 @@ __device__ __forceinline__ double ramlak_tap(int n, double tau)
 // Spectrum of the taps, in the forward transform's order, times scale / L.
 // Taps h[n] for -(W-1) <= n <= W-1: the Ram-Lak kernel (taps == nullptr)
 // or h[n] = taps[pad - n] (transpose: taps[K - 1 - (pad - n)]).
-__global__ __launch_bounds__(256) void fft_spectrum_kernel(FftConvArgs a)
+__global__ __launch_bounds__(kFftThreads) void fft_spectrum_kernel(FftConvArgs a)
 {
-    extern __shared__ double2 x[];
-    for (int p = threadIdx.x; p < a.L; p += kFftThreads) x[p] = {0.0, 0.0};
+    __shared__ double2 x[kFftLds];
+    for (int p = threadIdx.x; p < a.L; p += kFftThreads) x[px(p)] = {0.0, 0.0};
     __syncthreads();
     for (int n = -(a.W - 1) + (int)threadIdx.x; n <= a.W - 1; n += kFftThreads) {
         double h;
@@ -158,13 +166,13 @@ __global__ __launch_bounds__(256) void fft_spectrum_kernel(FftConvArgs a)
             const int t = a.pad - n;
             h = (t >= 0 && t < a.K) ? (double)a.taps[a.transpose ? a.K - 1 - t : t] : 0.0;
         }
-        x[n < 0 ? n + a.L : n] = {h, 0.0};
+        x[px(n < 0 ? n + a.L : n)] = {h, 0.0};
     }
     __syncthreads();
     fft_forward(x, a.L, a.log2L, a.tw);
     const double f = a.scale / (double)a.L;
     for (int p = threadIdx.x; p < a.L; p += kFftThreads)
-        a.spectrum[p] = {x[p].x * f, x[p].y * f};
+        a.spectrum[p] = {x[px(p)].x * f, x[px(p)].y * f};
 }
 
 __device__ __forceinline__ double parker_weight(double beta, double gamma, double delta)
@@ -225,9 +233,9 @@ __device__ __forceinline__ void store_sample(const FftConvArgs& a, int r, int j,
 }
 
 // Rows 2b and 2b + 1 (if any) of the call.
-__global__ __launch_bounds__(256) void fft_conv_kernel(FftConvArgs a)
+__global__ __launch_bounds__(kFftThreads) void fft_conv_kernel(FftConvArgs a)
 {
-    extern __shared__ double2 x[];
+    __shared__ double2 x[kFftLds];
     const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
     const bool two = r1 < a.rows;
     for (int p = threadIdx.x; p < a.L; p += kFftThreads) {
@@ -236,22 +244,21 @@ __global__ __launch_bounds__(256) void fft_conv_kernel(FftConvArgs a)
             re = row_sample(a, r0, p);
             if (two) im = row_sample(a, r1, p);
         }
-        x[p] = {re, im};
+        x[px(p)] = {re, im};
     }
     __syncthreads();
     fft_forward(x, a.L, a.log2L, a.tw);
-    for (int p = threadIdx.x; p < a.L; p += kFftThreads) x[p] = cmul(x[p], a.spectrum[p]);
+    for (int p = threadIdx.x; p < a.L; p += kFftThreads) x[px(p)] = cmul(x[px(p)], a.spectrum[p]);
     __syncthreads();
     fft_inverse(x, a.L, a.log2L, a.tw);
     for (int j = threadIdx.x; j < a.W; j += kFftThreads) {
-        store_sample(a, r0, j, x[j].x);
-        if (two) store_sample(a, r1, j, x[j].y);
+        store_sample(a, r0, j, x[px(j)].x);
+        if (two) store_sample(a, r1, j, x[px(j)].y);
     }
 }
 
 hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s)
 {
-    const size_t lds = (size_t)a.L * sizeof(double2);
     hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -262,10 +269,10 @@ hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s)
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fft_spectrum_kernel, dim3(1), dim3(kFftThreads), lds, s, a);
+    hipLaunchKernelGGL(fft_spectrum_kernel, dim3(1), dim3(kFftThreads), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fft_conv_kernel, dim3((a.rows + 1) / 2), dim3(kFftThreads), lds, s, a);
+    hipLaunchKernelGGL(fft_conv_kernel, dim3((a.rows + 1) / 2), dim3(kFftThreads), 0, s, a);
     return hipGetLastError();
 }
 
