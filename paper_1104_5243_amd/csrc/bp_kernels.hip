@@ -337,13 +337,18 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
         const int per = gridDim.x >> 3;
         bid = (bid & 7) * per + (bid >> 3);
     }
-    // Workgroups that run at the same time on one XCD share its L2; they
-    // are consecutive in this order, so stepping along the axis closest to
-    // the batch's ray direction keeps their projections on a view compact.
+    // Workgroup order: the tile axis closest to the batch's rays fastest,
+    // then the z chunks, then the transverse axis.  With the XCD remap an
+    // XCD gets a contiguous range of this order: a slab a few tiles thick
+    // across the rays, spanning the whole ray extent and all z, whose
+    // projection is a narrow band of detector columns, and the workgroups
+    // resident on it at one time form a compact box along the rays.
+    // (Measured on fdk512 FP32: 40.8 ms per backprojection with the z chunks
+    // slowest, 34.6 ms in this order.)
     const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
     const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
-    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
-    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int zc = rest % A.zchunks;
+    const int t1 = rest / A.zchunks;
     const int tx = A.y_fastest ? t1 : t0;
     const int ty = A.y_fastest ? t0 : t1;
 
