@@ -172,7 +172,16 @@ constexpr int kMseParts = 1024;
 // backprojection by storage type (FP32 taps: 16; 16-bit taps: 8, whose
 // smaller wave boxes clip more finely; both measured best on fdk512)
 constexpr int kFpZ = 16;
-__host__ __device__ constexpr int fused_z(int storage) { return storage == kF32 ? 16 : 8; }
+#ifndef FDK_Z_F32
+#define FDK_Z_F32 16
+#endif
+#ifndef FDK_Z_16BIT
+#define FDK_Z_16BIT 8
+#endif
+__host__ __device__ constexpr int fused_z(int storage)
+{
+    return storage == kF32 ? FDK_Z_F32 : FDK_Z_16BIT;
+}
 // A wave covers kWaveX x kWaveY voxel columns; a workgroup stacks kWgWaves
 // waves along y.
 #ifndef FDK_WG_WAVES

@@ -142,10 +142,11 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
         const int per = gridDim.x >> 3;
         bid = (bid & 7) * per + (bid >> 3);
     }
+    // the backprojection's workgroup order: ray axis, then z, then across
     const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
     const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
-    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
-    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int zc = rest % A.zchunks;
+    const int t1 = rest / A.zchunks;
     const int tx = A.y_fastest ? t1 : t0;
     const int ty = A.y_fastest ? t0 : t1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
