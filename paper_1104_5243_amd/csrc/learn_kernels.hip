@@ -222,17 +222,17 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
 template <int CIN, int COUT, int KT>
 struct WgradMfma {
     static constexpr int kChunk = 64;
-    static constexpr int kMT = COUT / 16;
-    static constexpr int kNT = CIN * KT / 16;
-    static constexpr int kNTW = (kNT + 3) / 4;  // n-tiles per wave (at most)
+    static constexpr int kMT = (COUT + 15) / 16;       // m-tiles (rows past COUT are zero)
+    static constexpr int kNN = CIN * KT;               // columns n = t * CIN + ci
+    static constexpr int kNT = (kNN + 15) / 16;        // n-tiles (columns past kNN are zero)
+    static constexpr int kNTW = (kNT + 3) / 4;         // n-tiles per wave (at most)
     static constexpr int kSpan = kChunk + KT - 1;
     static constexpr int kPitchX = pitch2(kSpan);
     static constexpr int kPitchD = pitch2(kChunk);
     static constexpr size_t lds_bytes()
     {
-        return (size_t)(COUT * kPitchD + CIN * kPitchX) * 4 + 256 * sizeof(double);
+        return (size_t)(16 * kMT * kPitchD + CIN * kPitchX) * 4 + 256 * sizeof(double);
     }
-    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel counts");
 };
 
 template <int CIN, int COUT, int KT>
@@ -241,18 +241,20 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int ch
 {
     using G = WgradMfma<CIN, COUT, KT>;
     extern __shared__ float lds[];
-    float* dy = lds;                          // [co][kPitchD]
-    float* xs = lds + COUT * G::kPitchD;      // [ci][kPitchX]
+    float* dy = lds;                               // [co][kPitchD], 16 kMT rows
+    float* xs = lds + 16 * G::kMT * G::kPitchD;    // [ci][kPitchX]
     double* red = (double*)(xs + CIN * G::kPitchX);
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     // per n-tile of this wave: offset of lane l's B fragment in the x tile
     int boff[G::kNTW];
+    bool bvalid[G::kNTW];
 #pragma unroll
     for (int k = 0; k < G::kNTW; ++k) {
-        const int n0 = (w + 4 * k) * 16;
-        const int t = n0 / CIN, ci = n0 % CIN + (l & 15);
-        boff[k] = ci * G::kPitchX + t + (l >> 4);
+        const int n = (w + 4 * k) * 16 + (l & 15);
+        bvalid[k] = n < G::kNN;
+        const int t = n / CIN, ci = n - t * CIN;
+        boff[k] = bvalid[k] ? ci * G::kPitchX + t + (l >> 4) : 0;
     }
     const int aoff = (l & 15) * G::kPitchD + (l >> 4);
     mf4 acc[G::kMT][G::kNTW];
@@ -272,10 +274,11 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int ch
         const float* drow = a.dout + (size_t)row * COUT * a.W;
         const float* xrow = a.in + (size_t)row * CIN * a.W;
         __syncthreads();
-        for (int e = threadIdx.x; e < COUT * G::kChunk; e += 256) {
+        for (int e = threadIdx.x; e < 16 * G::kMT * G::kChunk; e += 256) {
             const int co = e / G::kChunk, p = e - co * G::kChunk;
             const int j = j0 + p;
-            dy[co * G::kPitchD + p] = (j < a.W) ? drow[(size_t)co * a.W + j] : 0.0f;
+            dy[co * G::kPitchD + p] =
+                (co < COUT && j < a.W) ? drow[(size_t)co * a.W + j] : 0.0f;
         }
         for (int e = threadIdx.x; e < CIN * G::kSpan; e += 256) {
             const int ci = e / G::kSpan, sp = e - ci * G::kSpan;
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int ch
 #pragma unroll
             for (int k = 0; k < G::kNTW; ++k) {
                 if (w + 4 * k < G::kNT) {
-                    const float bv = xs[boff[k] + 4 * st];
+                    const float bv = bvalid[k] ? xs[boff[k] + 4 * st] : 0.0f;
 #pragma unroll
                     for (int mt = 0; mt < G::kMT; ++mt) acc[mt][k] = mfma16x16x4(av[mt], bv, acc[mt][k]);
                 }
@@ -319,13 +322,13 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int ch
     for (int mt = 0; mt < G::kMT; ++mt)
 #pragma unroll
         for (int k = 0; k < G::kNTW; ++k) {
-            if (w + 4 * k >= G::kNT) continue;
+            if (w + 4 * k >= G::kNT || !bvalid[k]) continue;
             const int n = (w + 4 * k) * 16 + (l & 15);
-            const int t = n / CIN, ci = n % CIN;
+            const int t = n / CIN, ci = n - t * CIN;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int co = mt * 16 + 4 * (l >> 4) + i;
-                part[((size_t)co * CIN + ci) * KT + t] = sum[mt][k][i];
+                if (co < COUT) part[((size_t)co * CIN + ci) * KT + t] = sum[mt][k][i];
             }
         }
     red[threadIdx.x] = accb;
@@ -518,11 +521,16 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(LearnGradArgs a, int 
 
 hipError_t launch_wgrad(const LearnGradArgs& a, int nblocks, hipStream_t s)
 {
+    const int cpr = (a.W + 63) / 64;  // 64-position chunks
     if (mfma_shape(a.cin, a.cout, a.K)) {
-        using G = WgradMfma<32, 32, 9>;
-        const int cpr = (a.W + G::kChunk - 1) / G::kChunk;
-        hipLaunchKernelGGL((wgrad_mfma_kernel<32, 32, 9>), dim3(nblocks), dim3(256), G::lds_bytes(),
-                           s, a, cpr, a.rows * cpr);
+        hipLaunchKernelGGL((wgrad_mfma_kernel<32, 32, 9>), dim3(nblocks), dim3(256),
+                           (WgradMfma<32, 32, 9>::lds_bytes()), s, a, cpr, a.rows * cpr);
+    } else if (a.K == 9 && a.cin == 1 && a.cout == 32) {
+        hipLaunchKernelGGL((wgrad_mfma_kernel<1, 32, 9>), dim3(nblocks), dim3(256),
+                           (WgradMfma<1, 32, 9>::lds_bytes()), s, a, cpr, a.rows * cpr);
+    } else if (a.K == 9 && a.cin == 32 && a.cout == 1) {
+        hipLaunchKernelGGL((wgrad_mfma_kernel<32, 1, 9>), dim3(nblocks), dim3(256),
+                           (WgradMfma<32, 1, 9>::lds_bytes()), s, a, cpr, a.rows * cpr);
     } else {
         const size_t lds =
             (size_t)(a.cout * kGradChunk + a.cin * (kGradChunk + a.K - 1)) * sizeof(float);
