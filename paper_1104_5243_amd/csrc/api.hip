@@ -405,6 +405,48 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     return FDK_OK;
 }
 
+// LDS tile of the forward projection: the largest detector footprint (with
+// the kernel's margins) of a 16^3 workgroup box at the volume's corners or
+// centre over the batch's views, rounded up to a power of two in
+// [8192, 32768] entries (32-128 KiB).  Boxes with a larger footprint fall
+// back to global atomics in the kernel.
+int fp_tile_entries(const float* mats, int cnt, int N)
+{
+    const double c = 0.5 * (N - 1);
+    const double e = std::min(15.0, (double)(N - 1));
+    double worst = 0.0;
+    for (int j = 0; j < cnt; ++j) {
+        const float* q = mats + 12 * (size_t)j;
+        for (int b = 0; b < 9; ++b) {
+            // box origin: a volume corner (b < 8) or the centre
+            const double bx = b == 8 ? -0.5 * e : ((b & 1) ? c - e : -c);
+            const double by = b == 8 ? -0.5 * e : ((b & 2) ? c - e : -c);
+            const double bz = b == 8 ? -0.5 * e : ((b & 4) ? c - e : -c);
+            double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+            bool ok = true;
+            for (int k = 0; k < 8; ++k) {
+                const double x = bx + ((k & 1) ? e : 0), y = by + ((k & 2) ? e : 0),
+                             z = bz + ((k & 4) ? e : 0);
+                const double w = q[8] * x + q[9] * y + q[10] * z + q[11];
+                if (!(w > 0.0)) ok = false;
+                const double u = (q[0] * x + q[1] * y + q[2] * z + q[3]) / w;
+                const double v = (q[4] * x + q[5] * y + q[6] * z + q[7]) / w;
+                umin = std::min(umin, u);
+                umax = std::max(umax, u);
+                vmin = std::min(vmin, v);
+                vmax = std::max(vmax, v);
+            }
+            if (!ok) continue;
+            const double area = (std::floor(umax) - std::floor(umin) + 4.0) *
+                                (std::floor(vmax) - std::floor(vmin) + 4.0);
+            worst = std::max(worst, area);
+        }
+    }
+    int cap = 8192;
+    while (cap < 32768 && cap < worst) cap <<= 1;
+    return cap;
+}
+
 int run_forward(float* proj, int n_views, int H, int W, const double* P, const float* volume,
                 int N, float voxel_size, const float* origin, hipStream_t stream)
 {
@@ -447,6 +489,7 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
             e = launch_scatter(A, wcheck, stream);
         } else {
             FusedArgs C = A;  // 16 x 16 column tiles
+            C.fp_tile = fp_tile_entries(st->host_mats + 12 * (size_t)v0, cnt, N);
             C.tiles_x = (N + 15) / 16;
             C.tiles_y = (N + 15) / 16;
             const long long blocks = (long long)C.tiles_x * C.tiles_y * C.zchunks;

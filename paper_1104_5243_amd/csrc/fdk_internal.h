@@ -66,6 +66,7 @@ struct FusedArgs {
     int xcd_remap;       // 1: spread consecutive tiles over XCD-local ranges
     int y_fastest;       // 1: consecutive workgroups step along y, else along x
     const float* m;      // count x 12 folded matrices of this batch (device memory)
+    int fp_tile;         // forward projection: entries of a workgroup's LDS tile
 };
 
 // Arguments of the plain kernel: world-coordinate matrices (FP32 roundings

@@ -131,11 +131,10 @@ hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
 // (error <= 2^-32 * 4096 * max|x| * max r^2 per tap); the tile sums are then
 // exact, independent of the order of the atomics.
 constexpr int kFpTile = 16;
-constexpr int kFpLds = 8192;  // floats of LDS tile
 
 __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
 {
-    __shared__ int tile[kFpLds];
+    extern __shared__ int tile[];  // A.fp_tile entries
     __shared__ float wave_max[4];
     int bid = blockIdx.x;
     if (A.xcd_remap) {
@@ -235,7 +234,7 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
         // outside [1e-20, 1e30] (or not finite) take the float path.
         const float rmax = 1.0f / wmin;
         const float bound = 4096.0f * vmax * rmax * rmax;
-        const bool use_lds = TW * TH <= kFpLds && bound >= 1e-20f && bound <= 1e30f;
+        const bool use_lds = TW * TH <= A.fp_tile && bound >= 1e-20f && bound <= 1e30f;
         const int k = min(max((int)floorf(__builtin_log2f(2147483648.0f / bound)) - 1, -100), 100);
         const float S = __builtin_ldexpf(1.0f, k), invS = __builtin_ldexpf(1.0f, -k);
         if (use_lds) {
@@ -299,7 +298,7 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
 hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s)
 {
     dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
-    hipLaunchKernelGGL(fp_lds_kernel, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(fp_lds_kernel, grid, dim3(256), (size_t)a.fp_tile * sizeof(int), s, a);
     return hipGetLastError();
 }
 
