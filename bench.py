@@ -76,6 +76,16 @@ def measured_traffic():
     return int(float(rec["hbm_bytes_per_launch"]))
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _timed(torch, fdk, fn, warmup, steps):
     """Wall time per step over `steps` calls (after `warmup`), and the mean
     duration of the library's kernels inside, from its HIP events."""
@@ -383,6 +393,19 @@ def main() -> int:
         "kernel_ms_per_step": round(kernel_ms / args.steps, 3),
         "kernel_gups": round(updates * args.steps / kernel_s / 1e9, 1),
     }
+    # the other bounds of the same kernel time: HBM at the algorithmic bytes
+    # (each view read once, one volume read-modify-write per launch) and at
+    # the measured traffic, if recorded
+    esz = {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
+    alg_bytes = 8.0 * N ** 3 * (launches // args.steps) + float(V) * H * W * esz
+    alg_tbs = alg_bytes * args.steps / kernel_s / 1e12
+    roofline["other_bounds"] = {
+        "hbm_algorithmic": {"achieved_TBps": round(alg_tbs, 3), "peak_TBps": PEAK_HBM_GBS / 1e3,
+                            "frac": round(alg_tbs / (PEAK_HBM_GBS / 1e3), 4)},
+        "hbm_measured": None if traffic is None else {
+            "achieved_TBps": round(traffic * launches / kernel_s / 1e12, 3),
+            "peak_TBps": PEAK_HBM_GBS / 1e3},
+    }
 
     out = {
         "metric": METRIC,
@@ -445,6 +468,44 @@ def main() -> int:
                       f"all {V} views, FP64, {tc:.1f} s",
         }
         log(f"oracle: {tc:.1f}s, relRMSE {out['rel_rmse_vs_oracle']:.3e}")
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+
+        # reduced-precision storage of the same stack on the same GPU
+        variants = {}
+        for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            st, sc = fdk.to_storage(proj_d, dt)
+            vol.zero_()
+            fdk.backproject(vol, st, geom.P, vs, origin, view_scale=sc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                vol.zero_()
+                fdk.backproject(vol, st, geom.P, vs, origin, view_scale=sc)
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t0) / 3
+            variants[name] = {"value": round(updates / ts / 1e9, 2), "unit": "GUP/s",
+                              "ms_per_step": round(ts * 1e3, 3)}
+            del st
+        out["storage_variants"] = variants
+        log(f"storage variants: {variants}")
+
+        # context, not the metric: the stack copied from pinned host memory
+        # (PCIe) and backprojected
+        host = torch.empty(proj_d.shape, dtype=proj_d.dtype, pin_memory=True)
+        host.copy_(proj_d)
+        dst = torch.empty_like(proj_d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dst.copy_(host, non_blocking=True)
+        vol.zero_()
+        fdk.backproject(vol, dst, geom.P, vs, origin)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out["pcie_inclusive_context"] = {
+            "value": round(updates / tp / 1e9, 2), "unit": "GUP/s", "ms": round(tp * 1e3, 3),
+            "note": f"H2D copy of the {proj_d.numel() * 4 / 1e9:.2f} GB FP32 stack from pinned "
+                    "memory + backprojection; not the metric"}
+        del host, dst
 
     if args.probe_hbm:
         a = torch.ones(512 * 1024 * 1024, device=dev)  # 2 GiB
