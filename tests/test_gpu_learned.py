@@ -132,6 +132,32 @@ def test_conv_long_forward_wgrad(env, W, rows):
     assert rel(dh.cpu().numpy(), rdh[0, 0]) <= 1e-6
 
 
+@pytest.mark.parametrize("W,rows", [(1300, 5), (2048, 2)])
+def test_conv_long_register_fft(env, W, rows):
+    """Rows of 1025..2048 samples take the L = 4096 FFT kernel that keeps
+    its passes in registers: forward with bias and accumulation, and the
+    transposed call.  The adjoint of the correlation with taps w at offset
+    pad is the correlation with the reversed taps at offset K - 1 - pad."""
+    torch, fdk, GL, dev = env
+    rng = np.random.default_rng(W + 7)
+    K, pad = 2 * W - 1, W - 1
+    x = rng.standard_normal((rows, 1, W))
+    h = rng.standard_normal((1, 1, K))
+    b = rng.standard_normal(1)
+    base = rng.standard_normal((rows, 1, W))
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    F = lambda a: a.astype(np.float32).astype(np.float64)
+    out = T(base)
+    fdk.conv_rows(out, T(x), T(h), T(b), rows, W, 1, 1, K, pad, fdk.CONV_ACCUMULATE)
+    ref = OL.conv(F(x), F(h), F(b), pad) + F(base)
+    assert rel(out.cpu().numpy(), ref) <= 1e-6
+    dx = torch.empty(rows, 1, W, device=dev)
+    fdk.conv_rows(dx, T(x), T(h), None, rows, W, 1, 1, K, K - 1 - pad, fdk.CONV_TRANSPOSE)
+    ref_t = OL.conv(F(x), F(h)[:, :, ::-1], None, K - 1 - pad)
+    torch.cuda.synchronize()
+    assert rel(dx.cpu().numpy(), ref_t) <= 1e-6
+
+
 def test_elementwise_kernels(env):
     torch, fdk, GL, dev = env
     rng = np.random.default_rng(2)

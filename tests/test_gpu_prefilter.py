@@ -34,7 +34,8 @@ def _gpu_prefilter(fdk, torch, dev, li, g, full_scan=False):
 
 
 @pytest.mark.parametrize("shape", [(6, 960, 1248), (5, 480, 624), (3, 7, 9), (3, 5, 2048),
-                                   (3, 4, 1), (4, 3, 2), (3, 9, 513)])
+                                   (3, 4, 1), (4, 3, 2), (3, 9, 513),
+                                   (3, 3, 1025)])
 def test_prefilter_parity(env, shape):
     torch, fdk, dev = env
     V, H, W = shape
