@@ -129,6 +129,38 @@ __device__ __forceinline__ mf4 mfma16x16x4(float a, float b, mf4 c)
 __host__ __device__ constexpr int pitch16(int n) { return ((n + 15) / 32) * 32 + 16; }
 __host__ __device__ constexpr int pitch2(int n) { return ((n + 29) / 32) * 32 + 2; }
 
+// A tile of ROWS x SPAN floats, row r taken from src + r * W at columns
+// j_first .. j_first + SPAN - 1 (zero outside [0, W) and for rows >= VALID),
+// moved into LDS (pitch PITCH) by 256 threads in two steps: fetch() issues
+// all of a thread's global loads into registers, put() stores them.  A
+// kernel that walks chunks fetches the next chunk before computing on the
+// current one, so the loads' latency hides behind that work.
+template <int ROWS, int VALID, int SPAN, int PITCH>
+struct TileCopy {
+    static constexpr int kN = (ROWS * SPAN + 255) / 256;
+    float r[kN];
+    __device__ __forceinline__ void fetch(const float* src, int W, int j_first)
+    {
+#pragma unroll
+        for (int k = 0; k < kN; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            const int row = e / SPAN, sp = e - row * SPAN;
+            const int j = j_first + sp;
+            r[k] = (e < ROWS * SPAN && row < VALID && j >= 0 && j < W)
+                       ? src[(size_t)row * W + j] : 0.0f;
+        }
+    }
+    __device__ __forceinline__ void put(float* dst) const
+    {
+#pragma unroll
+        for (int k = 0; k < kN; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            const int row = e / SPAN, sp = e - row * SPAN;
+            if (e < ROWS * SPAN) dst[row * PITCH + sp] = r[k];
+        }
+    }
+};
+
 // Convolution: a block owns 128 positions of one row at a time (wave w:
 // positions 32 w .. 32 w + 31, two 16-wide n-tiles) for all output
 // channels (two 16-wide m-tiles); the weights, stored as A fragments, stay
@@ -163,17 +195,20 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
         wl[e] = conv_weight(a, mt * 16 + (ll & 15), 4 * c4 + (ll >> 4), t);
     }
     const float* xb = xs + (l >> 4) * C::kPitch + w * 32 + (l & 15);
+    TileCopy<CIN, CIN, C::kSpan, C::kPitch> tile;
+    auto fetch = [&](int c) {
+        const int row = c / chunks_per_row;
+        const int j0 = (c - row * chunks_per_row) * C::kChunk;
+        tile.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
+    };
+    if (blockIdx.x < total_chunks) fetch(blockIdx.x);
     for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
         const int row = c / chunks_per_row;
         const int j0 = (c - row * chunks_per_row) * C::kChunk;
-        const float* in = a.in + (size_t)row * CIN * a.W;
         __syncthreads();  // the previous chunk's fragment reads are done
-        for (int e = threadIdx.x; e < CIN * C::kSpan; e += 256) {
-            const int ci = e / C::kSpan, sp = e - ci * C::kSpan;
-            const int j = j0 + sp - a.pad;
-            xs[ci * C::kPitch + sp] = (j >= 0 && j < a.W) ? in[(size_t)ci * a.W + j] : 0.0f;
-        }
+        tile.put(xs);
         __syncthreads();
+        if (c + (int)gridDim.x < total_chunks) fetch(c + gridDim.x);
         mf4 acc[C::kMT][2];
 #pragma unroll
         for (int mt = 0; mt < C::kMT; ++mt)
@@ -229,6 +264,10 @@ struct WgradMfma {
     static constexpr int kSpan = kChunk + KT - 1;
     static constexpr int kPitchX = pitch2(kSpan);
     static constexpr int kPitchD = pitch2(kChunk);
+    // waves per SIMD the register allocation aims at (fdk128 shapes, ms:
+    // 32->32 6.2 at the default, 4.2 at two waves; 1->32 1.0, 0.84; 32->1
+    // 2.7 at the default, 4.8 at two)
+    static constexpr int kMinWaves = COUT == 1 ? 1 : 2;
     static constexpr size_t lds_bytes()
     {
         return (size_t)(16 * kMT * kPitchD + CIN * kPitchX) * 4 + 256 * sizeof(double);
@@ -236,7 +275,7 @@ struct WgradMfma {
 };
 
 template <int CIN, int COUT, int KT>
-__global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int chunks_per_row,
+__global__ __launch_bounds__(256, (WgradMfma<CIN, COUT, KT>::kMinWaves)) void wgrad_mfma_kernel(LearnGradArgs a, int chunks_per_row,
                                                          int total_chunks)
 {
     using G = WgradMfma<CIN, COUT, KT>;
@@ -268,24 +307,21 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int ch
             for (int i = 0; i < 4; ++i) sum[mt][k][i] = 0.0;
         }
     double accb = 0.0;  // bias gradient: thread sums co = tid / 8, positions (tid % 8) * 8 ..
-    for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
+    TileCopy<16 * G::kMT, COUT, G::kChunk, G::kPitchD> dtile;
+    TileCopy<CIN, CIN, G::kSpan, G::kPitchX> xtile;
+    auto fetch = [&](int c) {
         const int row = c / chunks_per_row;
         const int j0 = (c - row * chunks_per_row) * G::kChunk;
-        const float* drow = a.dout + (size_t)row * COUT * a.W;
-        const float* xrow = a.in + (size_t)row * CIN * a.W;
+        dtile.fetch(a.dout + (size_t)row * COUT * a.W, a.W, j0);
+        xtile.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
+    };
+    if (blockIdx.x < total_chunks) fetch(blockIdx.x);
+    for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 16 * G::kMT * G::kChunk; e += 256) {
-            const int co = e / G::kChunk, p = e - co * G::kChunk;
-            const int j = j0 + p;
-            dy[co * G::kPitchD + p] =
-                (co < COUT && j < a.W) ? drow[(size_t)co * a.W + j] : 0.0f;
-        }
-        for (int e = threadIdx.x; e < CIN * G::kSpan; e += 256) {
-            const int ci = e / G::kSpan, sp = e - ci * G::kSpan;
-            const int j = j0 + sp - a.pad;
-            xs[ci * G::kPitchX + sp] = (j >= 0 && j < a.W) ? xrow[(size_t)ci * a.W + j] : 0.0f;
-        }
+        dtile.put(dy);
+        xtile.put(xs);
         __syncthreads();
+        if (c + (int)gridDim.x < total_chunks) fetch(c + gridDim.x);
 #pragma unroll
         for (int st = 0; st < G::kChunk / 4; ++st) {
             float av[G::kMT];
@@ -340,6 +376,103 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(LearnGradArgs a, int ch
     }
 }
 
+// Weight gradient of a layer with one output channel: dW[ci][t] = sum_p
+// x[ci][p] dy[p - t + pad] (the sum over j of dy[j] x[ci][j + t - pad] with
+// p = j + t - pad).  With input channels as the MFMA's rows, the KT taps as
+// its (one, zero-padded) column tile and positions as its k dimension, a
+// k-step takes CIN / 16 MFMAs, where the general kernel's 16-row tile over
+// the single output channel would take (CIN KT) / 16.  A block walks chunks
+// of 256 positions (64 per wave), adds the accumulators into FP64 sums after
+// each chunk, and combines its waves' sums in LDS for the fixed-order
+// reduction.
+template <int CIN, int KT>
+struct WgradC1 {
+    static constexpr int kChunk = 256;
+    static constexpr int kMT = CIN / 16;
+    static constexpr int kPitchX = kChunk + 4;  // rows 4 banks apart: conflict-free A reads
+    static constexpr int kSpanD = kChunk + KT - 1;
+    static constexpr int kNW = CIN * KT;
+    static constexpr size_t lds_bytes()
+    {
+        return (size_t)(CIN * kPitchX + kSpanD) * 4 + (size_t)(4 * kNW + 256) * sizeof(double);
+    }
+    static_assert(CIN % 16 == 0 && KT <= 16, "shape");
+    static_assert((CIN * kPitchX + kSpanD) % 2 == 0, "FP64 sums after the tiles stay aligned");
+};
+
+template <int CIN, int KT>
+__global__ __launch_bounds__(256) void wgrad_c1_kernel(LearnGradArgs a, int chunks_per_row,
+                                                       int total_chunks)
+{
+    using G = WgradC1<CIN, KT>;
+    extern __shared__ float lds[];
+    float* xt = lds;                          // [ci][kPitchX]
+    float* dt = xt + CIN * G::kPitchX;        // kSpanD: position j0 + s - (KT - 1 - pad)
+    double* red = (double*)(dt + G::kSpanD);  // [wave][ci * KT + t], then 256 bias sums
+    const int l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int n = l & 15;  // tap of this lane's B column and D column
+    const float* xa = xt + (l & 15) * G::kPitchX + w * 64 + (l >> 4);
+    const float* db = dt + w * 64 + (l >> 4) + KT - 1 - n;
+    mf4 acc[G::kMT];
+    double sum[G::kMT][4];
+#pragma unroll
+    for (int mt = 0; mt < G::kMT; ++mt) {
+        acc[mt] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sum[mt][i] = 0.0;
+    }
+    double accb = 0.0;
+    TileCopy<CIN, CIN, G::kChunk, G::kPitchX> xtile;
+    TileCopy<1, 1, G::kSpanD, G::kSpanD> dtile;
+    auto fetch = [&](int c) {
+        const int row = c / chunks_per_row;
+        const int j0 = (c - row * chunks_per_row) * G::kChunk;
+        xtile.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0);
+        dtile.fetch(a.dout + (size_t)row * a.W, a.W, j0 - (KT - 1 - a.pad));
+    };
+    if (blockIdx.x < total_chunks) fetch(blockIdx.x);
+    for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
+        __syncthreads();
+        xtile.put(xt);
+        dtile.put(dt);
+        __syncthreads();
+        if (c + (int)gridDim.x < total_chunks) fetch(c + gridDim.x);
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const float bv = n < KT ? db[4 * st] : 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < G::kMT; ++mt)
+                acc[mt] = mfma16x16x4(xa[mt * 16 * G::kPitchX + 4 * st], bv, acc[mt]);
+        }
+#pragma unroll
+        for (int mt = 0; mt < G::kMT; ++mt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sum[mt][i] += (double)acc[mt][i];
+            acc[mt] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        accb += (double)dt[threadIdx.x + KT - 1 - a.pad];  // position j0 + threadIdx.x
+    }
+    // D[m][n] of lane l: rows m = 4 (l >> 4) + i, column n = l & 15
+    if (n < KT) {
+#pragma unroll
+        for (int mt = 0; mt < G::kMT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                red[w * G::kNW + (mt * 16 + 4 * (l >> 4) + i) * KT + n] = sum[mt][i];
+    }
+    red[4 * G::kNW + threadIdx.x] = accb;
+    __syncthreads();
+    double* part = a.part + (size_t)blockIdx.x * (G::kNW + 1);
+    for (int e = threadIdx.x; e < G::kNW; e += 256)
+        part[e] = ((red[e] + red[G::kNW + e]) + red[2 * G::kNW + e]) + red[3 * G::kNW + e];
+    if (threadIdx.x == 0) {
+        double sb = 0.0;
+        for (int q = 0; q < 256; ++q) sb += red[4 * G::kNW + q];
+        part[G::kNW] = sb;
+    }
+}
+
 // the shapes the MFMA path takes
 __host__ __device__ constexpr bool mfma_shape(int cin, int cout, int K)
 {
@@ -360,11 +493,10 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
     __shared__ float tile[CIN * kSpan];
     const int row = blockIdx.y;
     const int j0 = blockIdx.x * 256;
-    const float* in = a.in + (size_t)row * CIN * a.W;
-    for (int e = threadIdx.x; e < CIN * kSpan; e += 256) {
-        const int ci = e / kSpan, sp = e - ci * kSpan;
-        const int j = j0 + sp - a.pad;
-        tile[e] = (j >= 0 && j < a.W) ? in[(size_t)ci * a.W + j] : 0.0f;
+    {
+        TileCopy<CIN, CIN, kSpan, kSpan> tc;
+        tc.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
+        tc.put(tile);
     }
     __syncthreads();
     const int j = j0 + threadIdx.x;
@@ -528,6 +660,11 @@ hipError_t launch_wgrad(const LearnGradArgs& a, int nblocks, hipStream_t s)
     } else if (a.K == 9 && a.cin == 1 && a.cout == 32) {
         hipLaunchKernelGGL((wgrad_mfma_kernel<1, 32, 9>), dim3(nblocks), dim3(256),
                            (WgradMfma<1, 32, 9>::lds_bytes()), s, a, cpr, a.rows * cpr);
+    } else if (a.K == 9 && a.cin == 32 && a.cout == 1 && a.pad <= 8) {
+        // (its bias sum reads dy tile entries 8 - pad .. 263 - pad)
+        const int cpr1 = (a.W + WgradC1<32, 9>::kChunk - 1) / WgradC1<32, 9>::kChunk;
+        hipLaunchKernelGGL((wgrad_c1_kernel<32, 9>), dim3(nblocks), dim3(256),
+                           (WgradC1<32, 9>::lds_bytes()), s, a, cpr1, a.rows * cpr1);
     } else if (a.K == 9 && a.cin == 32 && a.cout == 1) {
         hipLaunchKernelGGL((wgrad_mfma_kernel<32, 1, 9>), dim3(nblocks), dim3(256),
                            (WgradMfma<32, 1, 9>::lds_bytes()), s, a, cpr, a.rows * cpr);

@@ -71,6 +71,27 @@ def test_conv_short_forward_adjoint_wgrad(env, cin, cout, W, rows, relu):
     assert rel(out2.cpu().numpy(), out.cpu().numpy() + base) <= 1e-5
 
 
+@pytest.mark.parametrize("W,rows,pad", [(300, 5, 0), (257, 3, 8), (70, 4, 12), (513, 2, 4)])
+def test_wgrad_one_output_channel(env, W, rows, pad):
+    """32 -> 1 weight gradients: pad <= 8 takes the kernel with the input
+    channels as MFMA rows (chunks of 256 positions, ragged last chunk),
+    larger pads the general one; both against the oracle."""
+    torch, fdk, GL, dev = env
+    rng = np.random.default_rng(W * 10 + pad)
+    K = 9
+    x = rng.standard_normal((rows, 32, W)).astype(np.float32)
+    dy = rng.standard_normal((rows, 1, W)).astype(np.float32)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    dw = torch.empty(1, 32, K, device=dev)
+    db = torch.empty(1, device=dev)
+    ws = torch.empty(fdk.conv_rows_wgrad_workspace(32, 1, K) // 4, device=dev)
+    fdk.conv_rows_wgrad(dw, db, T(dy), T(x), rows, W, 32, 1, K, pad, ws)
+    rdw, rdb = OL.conv_wgrad(dy.astype(np.float64), x.astype(np.float64), K, pad)
+    torch.cuda.synchronize()
+    assert rel(dw.cpu().numpy(), rdw) <= 1e-5
+    assert rel(db.cpu().numpy(), rdb) <= 1e-5
+
+
 @pytest.mark.parametrize("W,rows,pad", [(624, 220, 4), (129, 6, 2), (1, 5, 4), (200, 300, 4)])
 def test_conv_mfma_path_shapes(env, W, rows, pad):
     """The 32 -> 32 channel, 9-tap layers run on matrix cores: forward,
