@@ -729,7 +729,10 @@ int fdk_conv_rows(float* out, const float* in, const float* weight, const float*
 size_t fdk_conv_rows_wgrad_workspace(int cin, int cout, int K)
 {
     if (cin < 1 || cout < 1 || K < 1) return 0;
-    return (size_t)kGradBlocks * ((size_t)cin * cout * K + cout) * sizeof(double);
+    const size_t direct = (size_t)kGradBlocks * ((size_t)cin * cout * K + cout) * sizeof(double);
+    // a single-channel ramp of K = 2W - 1 taps may take the FFT path
+    const size_t fft = cin == 1 && cout == 1 && K > 32 ? fft_xcorr_workspace(K) : 0;
+    return std::max(direct, fft);
 }
 
 int fdk_conv_rows_wgrad(float* dweight, float* dbias, const float* dout, const float* in, int rows,
@@ -752,6 +755,31 @@ int fdk_conv_rows_wgrad(float* dweight, float* dbias, const float* dout, const f
         return fail(FDK_ERR_UNSUPPORTED, "row too long for the LDS");
     if (!longk && (size_t)(cout * 128 + cin * (128 + K - 1)) * sizeof(float) > 65536)
         return fail(FDK_ERR_UNSUPPORTED, "channels too many for the LDS");
+    if (longk && K == 2 * W - 1 && pad == W - 1 && W <= kFftMax / 2) {
+        // the full-row ramp: cross-spectra through the FFT (FP64)
+        FftXcorrArgs X;
+        X.dweight = dweight;
+        X.dbias = dbias;
+        X.dout = dout;
+        X.in = in;
+        X.rows = rows;
+        X.W = W;
+        X.K = K;
+        X.pad = pad;
+        X.L = 4;
+        X.log2L = 2;
+        while (X.L < K) {
+            X.L <<= 1;
+            ++X.log2L;
+        }
+        X.blocks = std::max(1, std::min(kXcorrBlocks, (rows + 1) / 2));
+        X.tw = (double2*)workspace;
+        X.total = X.tw + kFftMax;
+        X.part = X.total + X.L;
+        X.bpart = (double*)(X.part + (size_t)kXcorrBlocks * X.L);
+        const hipError_t e = launch_fft_xcorr(X, (hipStream_t)stream);
+        return e == hipSuccess ? FDK_OK : hip_fail(e, "wgrad launch");
+    }
     LearnGradArgs A;
     A.dweight = dweight;
     A.dbias = dbias;

@@ -123,6 +123,28 @@ struct FftConvArgs {
 };
 hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s);
 
+// Weight (and bias) gradient of the full-row ramp (one channel, K = 2W - 1
+// taps, pad = W - 1) through the FFT: per-block FP64 sums of the row pairs'
+// cross-spectra, a fixed-order sum over the blocks, one inverse transform.
+struct FftXcorrArgs {
+    float* dweight;       // K taps
+    float* dbias;         // 1 value, may be null
+    const float* dout;    // rows x W
+    const float* in;      // rows x W
+    int rows, W, K, pad;  // K = 2W - 1, pad = W - 1
+    int L, log2L;         // transform length, a power of 2 >= max(4, K)
+    int blocks;           // partial-sum blocks
+    // workspace slices
+    double2* tw;          // kFftMax twiddles
+    double2* total;       // L: the summed cross-spectrum
+    double* bpart;        // blocks: bias partial sums
+    double2* part;        // blocks x L: the blocks' cross-spectrum sums
+};
+constexpr int kXcorrBlocks = 512;
+// workspace bytes of the FFT path for K taps (0 if K is not odd or too long)
+size_t fft_xcorr_workspace(int K);
+hipError_t launch_fft_xcorr(const FftXcorrArgs& a, hipStream_t s);
+
 struct LearnConvArgs {
     float* out;
     const float* in;

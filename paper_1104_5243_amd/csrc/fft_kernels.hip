@@ -617,6 +617,124 @@ __global__ __launch_bounds__(kF16Threads, 3) void fft_conv4096_kernel(FftConvArg
         }
 }
 
+// ---------------------------------------------------------------------------
+// Weight gradient of the full-row ramp.
+//
+// dweight[t] = sum_r sum_j dout[r][j] in[r][j + t - pad] = sum_r c_r[t - pad],
+// with c_r[s] = sum_j dy_r[j] x_r[j + s] the cross-correlation of row r's
+// output gradient with its input, whose spectrum is conj(DY_r) X_r (both
+// rows real, zero padded to L >= 2W - 1, so the circular correlation is the
+// linear one on |s| <= W - 1).  Two rows a, b are packed as z_x = x_a + i x_b
+// and z_d = dy_a + i dy_b; then conj(Z_d) Z_x = conj(DY_a) X_a + conj(DY_b) X_b
+// + i (conj(DY_a) X_b - conj(DY_b) X_a), whose first part transforms back to
+// the real signal c_a + c_b and the second to an imaginary one: the real part
+// of the inverse transform of the summed conj(Z_d) Z_x is sum_r c_r.  The
+// forward transforms leave the spectra in the same (digit-reversed) order,
+// so the products and sums are taken position by position, and the inverse
+// transform returns natural order.
+
+// Block b sums conj(Z_d) Z_x over row pairs b, b + blocks, ... into its slice
+// part[b] (each thread owns the positions p = threadIdx.x + 256 m), and the
+// output gradients' plain sum (the bias gradient) into bpart[b].
+__global__ __launch_bounds__(kFftThreads) void fft_xcorr_partial_kernel(FftXcorrArgs a)
+{
+    extern __shared__ double2 sm[];
+    const int span = a.L + a.L / 8;  // px(L - 1) < span
+    double2* zx = sm;
+    double2* zd = sm + span;
+    __shared__ double red[kFftThreads];
+    double2* S = a.part + (size_t)blockIdx.x * a.L;
+    for (int p = threadIdx.x; p < a.L; p += kFftThreads) S[p] = {0.0, 0.0};
+    double accb = 0.0;
+    const int pairs = (a.rows + 1) / 2;
+    for (int q = blockIdx.x; q < pairs; q += gridDim.x) {
+        const int r0 = 2 * q, r1 = r0 + 1;
+        const bool two = r1 < a.rows;
+        for (int p = threadIdx.x; p < a.L; p += kFftThreads) {
+            double2 vx = {0.0, 0.0}, vd = {0.0, 0.0};
+            if (p < a.W) {
+                vx.x = a.in[(size_t)r0 * a.W + p];
+                vd.x = a.dout[(size_t)r0 * a.W + p];
+                if (two) {
+                    vx.y = a.in[(size_t)r1 * a.W + p];
+                    vd.y = a.dout[(size_t)r1 * a.W + p];
+                }
+                accb += vd.x + vd.y;
+            }
+            zx[px(p)] = vx;
+            zd[px(p)] = vd;
+        }
+        __syncthreads();
+        fft_forward(zx, a.L, a.log2L, a.tw);
+        fft_forward(zd, a.L, a.log2L, a.tw);
+        for (int p = threadIdx.x; p < a.L; p += kFftThreads)
+            S[p] = cadd(S[p], cmulc(zx[px(p)], zd[px(p)]));
+        __syncthreads();  // the next pair overwrites zx and zd
+    }
+    red[threadIdx.x] = accb;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sb = 0.0;
+        for (int t = 0; t < kFftThreads; ++t) sb += red[t];
+        a.bpart[blockIdx.x] = sb;
+    }
+}
+
+// total[p] = sum over the blocks (in block order) of part[b][p]
+__global__ __launch_bounds__(256) void fft_xcorr_sum_kernel(FftXcorrArgs a)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.L) return;
+    double2 s = {0.0, 0.0};
+    for (int b = 0; b < a.blocks; ++b) s = cadd(s, a.part[(size_t)b * a.L + p]);
+    a.total[p] = s;
+}
+
+// One block: the inverse transform of the total, taps t <- lag t - pad.
+__global__ __launch_bounds__(kFftThreads) void fft_xcorr_final_kernel(FftXcorrArgs a)
+{
+    __shared__ double2 x[kFftLds];
+    for (int p = threadIdx.x; p < a.L; p += kFftThreads) x[px(p)] = a.total[p];
+    __syncthreads();
+    fft_inverse(x, a.L, a.log2L, a.tw);
+    const double f = 1.0 / (double)a.L;
+    for (int t = threadIdx.x; t < a.K; t += kFftThreads) {
+        int s = t - a.pad;
+        if (s < 0) s += a.L;
+        a.dweight[t] = (float)(x[px(s)].x * f);
+    }
+    if (threadIdx.x == 0 && a.dbias) {
+        double sb = 0.0;
+        for (int b = 0; b < a.blocks; ++b) sb += a.bpart[b];
+        a.dbias[0] = (float)sb;
+    }
+}
+
+size_t fft_xcorr_workspace(int K)
+{
+    if (K < 1 || !(K & 1) || K > kFftMax - 1) return 0;
+    int L = 4;
+    while (L < K) L <<= 1;
+    return ((size_t)kFftMax + L + (size_t)kXcorrBlocks * L) * sizeof(double2) +
+           (size_t)kXcorrBlocks * sizeof(double);
+}
+
+hipError_t launch_fft_xcorr(const FftXcorrArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)2 * (a.L + a.L / 8) * sizeof(double2);
+    hipLaunchKernelGGL(fft_xcorr_partial_kernel, dim3(a.blocks), dim3(kFftThreads), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fft_xcorr_sum_kernel, dim3((a.L + 255) / 256), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fft_xcorr_final_kernel, dim3(1), dim3(kFftThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw);

@@ -146,11 +146,18 @@ def test_conv_long_forward_wgrad(env, W, rows):
     assert rel(out.cpu().numpy(), OL.conv(x.astype(np.float64), h.astype(np.float64), None,
                                           pad)) <= 1e-6
     dh = torch.empty(K, device=dev)
+    db = torch.empty(1, device=dev)
     ws = torch.empty(fdk.conv_rows_wgrad_workspace(1, 1, K) // 4, device=dev)
-    fdk.conv_rows_wgrad(dh, None, T(dy), T(x), rows, W, 1, 1, K, pad, ws)
-    rdh, _ = OL.conv_wgrad(dy.astype(np.float64), x.astype(np.float64), K, pad)
+    fdk.conv_rows_wgrad(dh, db, T(dy), T(x), rows, W, 1, 1, K, pad, ws)
+    rdh, rdb = OL.conv_wgrad(dy.astype(np.float64), x.astype(np.float64), K, pad)
     torch.cuda.synchronize()
     assert rel(dh.cpu().numpy(), rdh[0, 0]) <= 1e-6
+    assert rel(db.cpu().numpy(), rdb) <= 1e-6
+    # a pad other than W - 1 takes the direct kernel
+    fdk.conv_rows_wgrad(dh, None, T(dy), T(x), rows, W, 1, 1, K, pad - 3, ws)
+    rdh3, _ = OL.conv_wgrad(dy.astype(np.float64), x.astype(np.float64), K, pad - 3)
+    torch.cuda.synchronize()
+    assert rel(dh.cpu().numpy(), rdh3[0, 0]) <= 1e-6
 
 
 @pytest.mark.parametrize("W,rows", [(1300, 5), (2048, 2)])
@@ -177,6 +184,13 @@ def test_conv_long_register_fft(env, W, rows):
     ref_t = OL.conv(F(x), F(h)[:, :, ::-1], None, K - 1 - pad)
     torch.cuda.synchronize()
     assert rel(dx.cpu().numpy(), ref_t) <= 1e-6
+    # the taps' gradient (FFT cross-spectra at L = 4096)
+    dh = torch.empty(K, device=dev)
+    ws = torch.empty(fdk.conv_rows_wgrad_workspace(1, 1, K) // 4, device=dev)
+    fdk.conv_rows_wgrad(dh, None, T(base), T(x), rows, W, 1, 1, K, pad, ws)
+    rdh, _ = OL.conv_wgrad(F(base), F(x), K, pad)
+    torch.cuda.synchronize()
+    assert rel(dh.cpu().numpy(), rdh[0, 0]) <= 1e-6
 
 
 def test_elementwise_kernels(env):
