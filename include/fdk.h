@@ -154,6 +154,10 @@ int fdk_prefilter(float* out, const float* in, int n_views, int H, int W, double
 #define FDK_CONV_RELU 1       /* max(0, .) on the result */
 #define FDK_CONV_ACCUMULATE 2 /* add the existing output before the ReLU */
 #define FDK_CONV_TRANSPOSE 4  /* the adjoint convolution (data gradient) */
+/* keep the result where out > 0 on entry and store 0 elsewhere: with out
+ * holding a ReLU's output, this applies that ReLU's backward step to the
+ * result (which overwrites it); excludes FDK_CONV_RELU and _ACCUMULATE */
+#define FDK_CONV_RELU_MASK 8
 
 /*
  * fdk_conv_rows - batched 1D convolution along rows with zero extension:

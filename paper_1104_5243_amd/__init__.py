@@ -238,7 +238,7 @@ def prefilter(out, proj, beta0: float, dbeta: float, delta: float, sid: float, s
 # --------------------------------------------------------------------------
 # learned-filter kernels (thin wrappers; tensors are float32 CUDA tensors)
 # --------------------------------------------------------------------------
-CONV_RELU, CONV_ACCUMULATE, CONV_TRANSPOSE = 1, 2, 4
+CONV_RELU, CONV_ACCUMULATE, CONV_TRANSPOSE, CONV_RELU_MASK = 1, 2, 4, 8
 
 
 def _p(t):

@@ -676,8 +676,10 @@ int fdk_conv_rows(float* out, const float* in, const float* weight, const float*
         return fail(FDK_ERR_INVALID_ARG, "bad sizes rows=%d W=%d cin=%d cout=%d K=%d", rows, W,
                     cin, cout, K);
     if (pad < 0 || pad >= K + W) return fail(FDK_ERR_INVALID_ARG, "pad=%d out of range", pad);
-    if (flags & ~(FDK_CONV_RELU | FDK_CONV_ACCUMULATE | FDK_CONV_TRANSPOSE))
+    if (flags & ~(FDK_CONV_RELU | FDK_CONV_ACCUMULATE | FDK_CONV_TRANSPOSE | FDK_CONV_RELU_MASK))
         return fail(FDK_ERR_INVALID_ARG, "unknown flags %d", flags);
+    if ((flags & FDK_CONV_RELU_MASK) && (flags & (FDK_CONV_RELU | FDK_CONV_ACCUMULATE)))
+        return fail(FDK_ERR_INVALID_ARG, "FDK_CONV_RELU_MASK excludes RELU and ACCUMULATE");
     const bool shortk = K <= 32 && cout <= 64 && cin <= 64;
     const bool longk = cin == 1 && cout == 1 && K <= 8191;
     if (!shortk && !longk)
@@ -702,9 +704,10 @@ int fdk_conv_rows(float* out, const float* in, const float* weight, const float*
         F.bias = bias;
         F.relu = (flags & FDK_CONV_RELU) ? 1 : 0;
         F.accumulate = (flags & FDK_CONV_ACCUMULATE) ? 1 : 0;
+        F.mask = (flags & FDK_CONV_RELU_MASK) ? 1 : 0;
         return run_fft_conv(F, (hipStream_t)stream);
     }
-    LearnConvArgs A;
+    LearnConvArgs A = {};
     A.out = out;
     A.in = in;
     A.weight = weight;
@@ -718,6 +721,7 @@ int fdk_conv_rows(float* out, const float* in, const float* weight, const float*
     A.relu = (flags & FDK_CONV_RELU) ? 1 : 0;
     A.accumulate = (flags & FDK_CONV_ACCUMULATE) ? 1 : 0;
     A.transpose = (flags & FDK_CONV_TRANSPOSE) ? 1 : 0;
+    A.mask = (flags & FDK_CONV_RELU_MASK) ? 1 : 0;
     hipEvent_t t0;
     int rc = timed_begin((hipStream_t)stream, &t0);
     if (rc != FDK_OK) return rc;

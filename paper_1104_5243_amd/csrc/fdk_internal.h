@@ -117,9 +117,10 @@ struct FftConvArgs {
     double beta0, dbeta, delta, sdd, pixel;
     double* parker;
     double* cosw;
-    // output: + bias[0] (if not null), + out (accumulate), ReLU
+    // output: + bias[0] (if not null), + out (accumulate), ReLU, and kept
+    // only where out > 0 on entry (mask)
     const float* bias;
-    int accumulate, relu;
+    int accumulate, relu, mask;
 };
 hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s);
 
@@ -152,6 +153,7 @@ struct LearnConvArgs {
     const float* bias;   // may be null
     int rows, W, cin, cout, K, pad;
     int relu, accumulate, transpose;
+    int mask;            // keep the result where out > 0 on entry, else 0
 };
 
 struct LearnGradArgs {

@@ -319,6 +319,7 @@ __device__ __forceinline__ void store_sample(const FftConvArgs& a, int r, int j,
     if (a.bias) v += a.bias[0];
     if (a.accumulate) v += *o;
     if (a.relu) v = fmaxf(v, 0.0f);
+    if (a.mask) v = *o > 0.0f ? v : 0.0f;
     *o = v;
 }
 

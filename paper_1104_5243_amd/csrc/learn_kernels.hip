@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void conv_short_kernel(LearnConvArgs a)
                 float* o = out + (size_t)co * a.W + j;
                 if (a.accumulate) v += *o;
                 if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.mask) v = *o > 0.0f ? v : 0.0f;
                 *o = v;
             }
         }
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(256) void conv_long_kernel(LearnConvArgs a)
     float v = (float)acc;
     if (a.accumulate) v += *o;
     if (a.relu) v = fmaxf(v, 0.0f);
+    if (a.mask) v = *o > 0.0f ? v : 0.0f;
     *o = v;
 }
 
@@ -242,6 +244,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
                     float* o = out + (size_t)co * a.W + j;
                     if (a.accumulate) v += *o;
                     if (a.relu) v = fmaxf(v, 0.0f);
+                    if (a.mask) v = *o > 0.0f ? v : 0.0f;
                     *o = v;
                 }
             }
@@ -515,6 +518,7 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
             float* o = out + (size_t)co * a.W;
             if (a.accumulate) acc += *o;
             if (a.relu) acc = fmaxf(acc, 0.0f);
+            if (a.mask) acc = *o > 0.0f ? acc : 0.0f;
             *o = acc;
         }
     } else {
@@ -525,6 +529,7 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
             for (int t = 0; t < KT; ++t) acc = fmaf(conv_weight(a, 0, ci, t), x[ci * kSpan + t], acc);
         if (a.accumulate) acc += *out;
         if (a.relu) acc = fmaxf(acc, 0.0f);
+        if (a.mask) acc = *out > 0.0f ? acc : 0.0f;
         *out = acc;
     }
 }

@@ -34,8 +34,8 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import (CONV_RELU, CONV_TRANSPOSE, adam, backproject, conv_rows, conv_rows_wgrad,
-               conv_rows_wgrad_workspace, forward_project, group_dot, matvec, mse, relu_backward,
+from . import (CONV_RELU, CONV_RELU_MASK, CONV_TRANSPOSE, adam, backproject, conv_rows,
+               conv_rows_wgrad, conv_rows_wgrad_workspace, forward_project, group_dot, matvec, mse,
                scale_groups)
 
 FFT_LEN = 2048
@@ -218,16 +218,18 @@ class LearnedFilter:
         grads["W3"] = torch.empty_like(self.W3)
         grads["b3"] = torch.empty_like(self.b3)
         conv_rows_wgrad(grads["W3"], grads["b3"], dc, c["a2"], R, W, CH, 1, KC, KC // 2, self.ws)
-        da2 = torch.empty(R, CH, W, device=self.dev)
-        conv_rows(da2, dc, self.W3, None, R, W, 1, CH, KC, KC - 1 - KC // 2, CONV_TRANSPOSE)
-        relu_backward(da2, da2, c["a2"])
+        # the ReLU's backward step rides on the data-gradient convolution,
+        # which overwrites the activation it masks by (no longer needed)
+        da2 = c.pop("a2")
+        conv_rows(da2, dc, self.W3, None, R, W, 1, CH, KC, KC - 1 - KC // 2,
+                  CONV_TRANSPOSE | CONV_RELU_MASK)
         grads["W2"] = torch.empty_like(self.W2)
         grads["b2"] = torch.empty_like(self.b2)
         conv_rows_wgrad(grads["W2"], grads["b2"], da2, c["a1"], R, W, CH, CH, KC, KC // 2, self.ws)
-        da1 = torch.empty(R, CH, W, device=self.dev)
-        conv_rows(da1, da2, self.W2, None, R, W, CH, CH, KC, KC - 1 - KC // 2, CONV_TRANSPOSE)
+        da1 = c.pop("a1")
+        conv_rows(da1, da2, self.W2, None, R, W, CH, CH, KC, KC - 1 - KC // 2,
+                  CONV_TRANSPOSE | CONV_RELU_MASK)
         del da2
-        relu_backward(da1, da1, c["a1"])
         grads["W1"] = torch.empty_like(self.W1)
         grads["b1"] = torch.empty_like(self.b1)
         conv_rows_wgrad(grads["W1"], grads["b1"], da1, c["z"], R, W, 1, CH, KC, KC // 2, self.ws)

@@ -29,6 +29,21 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_conv_flag_constants_match_header():
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define FDK_CONV_(\w+) (\d+)", text))
+    assert defs and {k: int(v) for k, v in defs.items()} == {
+        k: getattr(fdk, "CONV_" + k) for k in defs}
+
+
+@pytest.mark.parametrize("extra", [1, 2])
+def test_conv_relu_mask_excludes_relu_and_accumulate(extra):
+    rc = fdk.lib().fdk_conv_rows(FAKE, FAKE, FAKE, None, 4, 16, 32, 32, 9, 4,
+                                 fdk.CONV_RELU_MASK | extra, None)
+    assert rc == fdk.FDK_ERR_INVALID_ARG
+    assert "RELU_MASK" in fdk.last_error()
+
+
 def test_version():
     assert fdk.version() >> 16 == 1
 

@@ -54,8 +54,14 @@ def test_conv_short_forward_adjoint_wgrad(env, cin, cout, W, rows, relu):
     assert rel(out.cpu().numpy(), ref) <= 1e-5
     dx = torch.empty(rows, cin, W, device=dev)
     fdk.conv_rows(dx, T(dy), T(w), None, rows, W, cout, cin, K, K - 1 - pad, fdk.CONV_TRANSPOSE)
-    assert rel(dx.cpu().numpy(), OL.conv_adjoint(dy.astype(np.float64), w.astype(np.float64),
-                                                 pad)) <= 1e-5
+    rdx = OL.conv_adjoint(dy.astype(np.float64), w.astype(np.float64), pad)
+    assert rel(dx.cpu().numpy(), rdx) <= 1e-5
+    # ReLU-masked data gradient: out holds the activation on entry
+    act = rng.standard_normal((rows, cin, W)).astype(np.float32)
+    dxm = T(act)
+    fdk.conv_rows(dxm, T(dy), T(w), None, rows, W, cout, cin, K, K - 1 - pad,
+                  fdk.CONV_TRANSPOSE | fdk.CONV_RELU_MASK)
+    assert rel(dxm.cpu().numpy(), np.where(act > 0, rdx, 0.0)) <= 1e-5
     dw = torch.empty(cout, cin, K, device=dev)
     db = torch.empty(cout, device=dev)
     ws = torch.empty(fdk.conv_rows_wgrad_workspace(cin, cout, K) // 4, device=dev)
@@ -184,6 +190,11 @@ def test_conv_long_register_fft(env, W, rows):
     ref_t = OL.conv(F(x), F(h)[:, :, ::-1], None, K - 1 - pad)
     torch.cuda.synchronize()
     assert rel(dx.cpu().numpy(), ref_t) <= 1e-6
+    dxm = T(base)
+    fdk.conv_rows(dxm, T(x), T(h), None, rows, W, 1, 1, K, K - 1 - pad,
+                  fdk.CONV_TRANSPOSE | fdk.CONV_RELU_MASK)
+    torch.cuda.synchronize()
+    assert rel(dxm.cpu().numpy(), np.where(F(base) > 0, ref_t, 0.0)) <= 1e-6
     # the taps' gradient (FFT cross-spectra at L = 4096)
     dh = torch.empty(K, device=dev)
     ws = torch.empty(fdk.conv_rows_wgrad_workspace(1, 1, K) // 4, device=dev)
