@@ -20,6 +20,8 @@
 //   fixed-order reduction over the blocks (deterministic).
 #include "fdk_internal.h"
 
+#include <algorithm>
+
 namespace fdk {
 
 constexpr int kShortTile = 64;
@@ -211,6 +213,21 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
         tile.put(xs);
         __syncthreads();
         if (c + (int)gridDim.x < total_chunks) fetch(c + gridDim.x);
+        float* out = a.out + (size_t)row * COUT * a.W;
+        // values the output holds (mask, accumulate), read before the MFMA work
+        float old[C::kMT][2][4];
+        if (a.mask || a.accumulate) {
+#pragma unroll
+            for (int mt = 0; mt < C::kMT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    const int j = j0 + w * 32 + nt * 16 + (l & 15);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        old[mt][nt][i] =
+                            j < a.W ? out[(size_t)(mt * 16 + 4 * (l >> 4) + i) * a.W + j] : 0.0f;
+                }
+        }
         mf4 acc[C::kMT][2];
 #pragma unroll
         for (int mt = 0; mt < C::kMT; ++mt)
@@ -230,7 +247,6 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
                 }
             }
         }
-        float* out = a.out + (size_t)row * COUT * a.W;
 #pragma unroll
         for (int mt = 0; mt < C::kMT; ++mt) {
 #pragma unroll
@@ -241,11 +257,10 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
                 for (int i = 0; i < 4; ++i) {
                     const int co = mt * 16 + 4 * (l >> 4) + i;
                     float v = acc[mt][nt][i] + (a.bias ? a.bias[co] : 0.0f);
-                    float* o = out + (size_t)co * a.W + j;
-                    if (a.accumulate) v += *o;
+                    if (a.accumulate) v += old[mt][nt][i];
                     if (a.relu) v = fmaxf(v, 0.0f);
-                    if (a.mask) v = *o > 0.0f ? v : 0.0f;
-                    *o = v;
+                    if (a.mask) v = old[mt][nt][i] > 0.0f ? v : 0.0f;
+                    out[(size_t)co * a.W + j] = v;
                 }
             }
         }
@@ -486,9 +501,11 @@ __host__ __device__ constexpr bool mfma_shape(int cin, int cout, int K)
 // narrow layers (one channel in or out, 9 taps): memory-bound
 // ---------------------------------------------------------------------------
 // One thread per output position, 256 positions per block, the input tile
-// (CIN x (256 + KT - 1)) in LDS; the weights are wave-uniform (compile-time
-// indices, scalar loads).  CIN = 1: the thread forms all COUT outputs from
-// its KT inputs; COUT = 1: it sums CIN x KT products.
+// (CIN x (256 + KT - 1)) in LDS, its global loads all issued before any is
+// stored; the weights are wave-uniform (compile-time indices, scalar loads).
+// CIN = 1: the thread forms all COUT outputs from its KT inputs; COUT = 1: it
+// sums CIN x KT products.  With a.mask or a.accumulate the COUT values the
+// output holds are read up front, not one per output store.
 template <int CIN, int COUT, int KT>
 __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
 {
@@ -501,10 +518,15 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
         tc.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
         tc.put(tile);
     }
-    __syncthreads();
     const int j = j0 + threadIdx.x;
-    if (j >= a.W) return;
     float* out = a.out + (size_t)row * COUT * a.W + j;
+    float old[COUT];
+    if ((a.mask || a.accumulate) && j < a.W) {
+#pragma unroll
+        for (int co = 0; co < COUT; ++co) old[co] = out[(size_t)co * a.W];
+    }
+    __syncthreads();
+    if (j >= a.W) return;
     const float* x = tile + threadIdx.x;
     if (CIN == 1) {
         float xv[KT];
@@ -515,11 +537,10 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
             float acc = a.bias ? a.bias[co] : 0.0f;
 #pragma unroll
             for (int t = 0; t < KT; ++t) acc = fmaf(conv_weight(a, co, 0, t), xv[t], acc);
-            float* o = out + (size_t)co * a.W;
-            if (a.accumulate) acc += *o;
+            if (a.accumulate) acc += old[co];
             if (a.relu) acc = fmaxf(acc, 0.0f);
-            if (a.mask) acc = *o > 0.0f ? acc : 0.0f;
-            *o = acc;
+            if (a.mask) acc = old[co] > 0.0f ? acc : 0.0f;
+            out[(size_t)co * a.W] = acc;
         }
     } else {
         float acc = a.bias ? a.bias[0] : 0.0f;
@@ -527,9 +548,9 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
         for (int ci = 0; ci < CIN; ++ci)
 #pragma unroll
             for (int t = 0; t < KT; ++t) acc = fmaf(conv_weight(a, 0, ci, t), x[ci * kSpan + t], acc);
-        if (a.accumulate) acc += *out;
+        if (a.accumulate) acc += old[0];
         if (a.relu) acc = fmaxf(acc, 0.0f);
-        if (a.mask) acc = *out > 0.0f ? acc : 0.0f;
+        if (a.mask) acc = old[0] > 0.0f ? acc : 0.0f;
         *out = acc;
     }
 }
@@ -648,8 +669,16 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(LearnGradArgs a, int 
     const int nw = a.cout * a.cin * a.K;
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= nw + a.cout) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += a.part[(size_t)b * (nw + a.cout) + e];
+    // eight interleaved partial sums (loads in flight), added in a fixed order
+    const size_t stride = (size_t)nw + a.cout;
+    double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 8 <= nblocks; b += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] += a.part[(size_t)(b + k) * stride + e];
+    }
+    for (; b < nblocks; ++b) p[0] += a.part[(size_t)b * stride + e];
+    const double s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
     if (e < nw)
         a.dweight[e] = (float)s;
     else if (a.dbias)
@@ -757,16 +786,25 @@ __global__ __launch_bounds__(256) void scale_groups_kernel(float* y, const float
 }
 
 // out[g] = sum_i a[g][i] * b[g][i] (FP64, one block per group)
-__global__ __launch_bounds__(256) void group_dot_kernel(float* out, const float* a, const float* b,
-                                                        size_t len)
+// out[g] = sum_i a[g][i] b[g][i] in FP64: one 1024-thread block per group,
+// eight partial sums per thread (loads in flight), then a fixed-order tree.
+__global__ __launch_bounds__(1024) void group_dot_kernel(float* out, const float* a,
+                                                         const float* b, size_t len)
 {
-    __shared__ double red[256];
+    __shared__ double red[1024];
     const size_t base = (size_t)blockIdx.x * len;
-    double s = 0.0;
-    for (size_t i = threadIdx.x; i < len; i += 256) s += (double)a[base + i] * (double)b[base + i];
-    red[threadIdx.x] = s;
+    const float* pa = a + base;
+    const float* pb = b + base;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    size_t i = threadIdx.x;
+    for (; i + 7 * 1024 < len; i += 8 * 1024) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += (double)pa[i + 1024 * k] * (double)pb[i + 1024 * k];
+    }
+    for (; i < len; i += 1024) s[0] += (double)pa[i] * (double)pb[i];
+    red[threadIdx.x] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -782,19 +820,48 @@ __global__ __launch_bounds__(256) void relu_backward_kernel(float* dx, const flo
         dx[i] = y[i] > 0.0f ? dy[i] : 0.0f;
 }
 
-// y = A x (A rows x cols, row-major) or y = A^T x; FP64 accumulation
+// y = A x (A rows x cols, row-major) or y = A^T x; FP64 accumulation in a
+// fixed order.  A x: one wave per output row, lane l taking the columns
+// l + 64 k into four partial sums, the lanes then added by a butterfly (lane
+// 0's result is stored).  A^T x: a block per 64 outputs (one per lane), its
+// four waves taking the rows w + 4 k, added in wave order through LDS.
 __global__ __launch_bounds__(256) void matvec_kernel(float* y, const float* A, const float* x,
                                                      int rows, int cols, int transpose)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int n_out = transpose ? cols : rows;
-    if (i >= n_out) return;
-    double s = 0.0;
-    if (!transpose)
-        for (int c = 0; c < cols; ++c) s = fma((double)A[(size_t)i * cols + c], (double)x[c], s);
-    else
-        for (int r = 0; r < rows; ++r) s = fma((double)A[(size_t)r * cols + i], (double)x[r], s);
-    y[i] = (float)s;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (!transpose) {
+        const int i = blockIdx.x * 4 + w;
+        if (i >= rows) return;
+        const float* Ai = A + (size_t)i * cols;
+        int c = l;
+        for (; c + 192 < cols; c += 256) {
+            s0 = fma((double)Ai[c], (double)x[c], s0);
+            s1 = fma((double)Ai[c + 64], (double)x[c + 64], s1);
+            s2 = fma((double)Ai[c + 128], (double)x[c + 128], s2);
+            s3 = fma((double)Ai[c + 192], (double)x[c + 192], s3);
+        }
+        for (; c < cols; c += 64) s0 = fma((double)Ai[c], (double)x[c], s0);
+        double t = (s0 + s1) + (s2 + s3);
+        for (int m = 32; m > 0; m >>= 1) t += __shfl_xor(t, m);
+        if (l == 0) y[i] = (float)t;
+        return;
+    }
+    __shared__ double red[4][64];
+    const int i = blockIdx.x * 64 + l;
+    if (i < cols) {
+        int r = w;
+        for (; r + 12 < rows; r += 16) {
+            s0 = fma((double)A[(size_t)r * cols + i], (double)x[r], s0);
+            s1 = fma((double)A[(size_t)(r + 4) * cols + i], (double)x[r + 4], s1);
+            s2 = fma((double)A[(size_t)(r + 8) * cols + i], (double)x[r + 8], s2);
+            s3 = fma((double)A[(size_t)(r + 12) * cols + i], (double)x[r + 12], s3);
+        }
+        for (; r < rows; r += 4) s0 = fma((double)A[(size_t)r * cols + i], (double)x[r], s0);
+    }
+    red[w][l] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (w == 0 && i < cols) y[i] = (float)(((red[0][l] + red[1][l]) + red[2][l]) + red[3][l]);
 }
 
 // Adam (Kingma and Ba, 2015) with bias correction, step t >= 1
@@ -860,7 +927,7 @@ hipError_t launch_scale_groups(float* y, const float* x, const float* scale, siz
 hipError_t launch_group_dot(float* out, const float* a, const float* b, size_t len, int groups,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(group_dot_kernel, dim3(groups), dim3(256), 0, s, out, a, b, len);
+    hipLaunchKernelGGL(group_dot_kernel, dim3(groups), dim3(1024), 0, s, out, a, b, len);
     return hipGetLastError();
 }
 
@@ -873,8 +940,8 @@ hipError_t launch_relu_backward(float* dx, const float* dy, const float* y, size
 hipError_t launch_matvec(float* y, const float* A, const float* x, int rows, int cols,
                          int transpose, hipStream_t s)
 {
-    const int n = transpose ? cols : rows;
-    hipLaunchKernelGGL(matvec_kernel, dim3((n + 255) / 256), dim3(256), 0, s, y, A, x, rows, cols,
+    const int blocks = transpose ? (cols + 63) / 64 : (rows + 3) / 4;
+    hipLaunchKernelGGL(matvec_kernel, dim3(blocks), dim3(256), 0, s, y, A, x, rows, cols,
                        transpose);
     return hipGetLastError();
 }

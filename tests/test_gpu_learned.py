@@ -204,6 +204,39 @@ def test_conv_long_register_fft(env, W, rows):
     assert rel(dh.cpu().numpy(), rdh[0, 0]) <= 1e-6
 
 
+@pytest.mark.parametrize("rows,cols", [(7, 11), (1247, 1025), (5, 300), (300, 5)])
+def test_matvec_shapes(env, rows, cols):
+    """A x (a wave per row: four partial sums over columns, tails) and A^T x
+    (a block per 64 outputs: rows split over four waves, tails)."""
+    torch, fdk, GL, dev = env
+    rng = np.random.default_rng(rows * 7 + cols)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    A = rng.standard_normal((rows, cols)).astype(np.float32)
+    v = rng.standard_normal(cols).astype(np.float32)
+    u = rng.standard_normal(rows).astype(np.float32)
+    r1 = torch.empty(rows, device=dev)
+    fdk.matvec(r1, T(A), T(v), rows, cols)
+    r2 = torch.empty(cols, device=dev)
+    fdk.matvec(r2, T(A), T(u), rows, cols, transpose=True)
+    torch.cuda.synchronize()
+    assert rel(r1.cpu().numpy(), A.astype(np.float64) @ v) <= 1e-6
+    assert rel(r2.cpu().numpy(), A.astype(np.float64).T @ u) <= 1e-6
+
+
+@pytest.mark.parametrize("groups,len_", [(3, 20000), (2, 8 * 1024), (4, 8 * 1024 + 5)])
+def test_group_dot_long_groups(env, groups, len_):
+    """Groups longer than one pass of 1024 threads x 8 partial sums."""
+    torch, fdk, GL, dev = env
+    rng = np.random.default_rng(len_)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    a = rng.standard_normal((groups, len_)).astype(np.float32)
+    b = rng.standard_normal((groups, len_)).astype(np.float32)
+    out = torch.empty(groups, device=dev)
+    fdk.group_dot(out, T(a), T(b), len_, groups)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.cpu().numpy(), (a.astype(np.float64) * b).sum(1), rtol=1e-5)
+
+
 def test_elementwise_kernels(env):
     torch, fdk, GL, dev = env
     rng = np.random.default_rng(2)
