@@ -42,7 +42,8 @@ PAPER_GUPS = 3.79
 # the sources the fused kernel's launches depend on (kernel, argument
 # structs, device helpers, host set-up with its default layout)
 KERNEL_SRC = [os.path.join(ROOT, "paper_1104_5243_amd", "csrc", f)
-              for f in ("bp_kernels.hip", "gfx950_util.h", "fdk_internal.h", "api.hip")]
+              for f in ("bp_kernels.hip", "gfx950_util.h", "fdk_internal.h", "api_internal.h",
+                        "api.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bp_fused_fdk512_traffic.txt")
 
 

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfdk.so")
-SOURCES = ["api.hip", "bp_kernels.hip", "fp_kernels.hip", "fft_kernels.hip",
+SOURCES = ["api.hip", "api_learn.hip", "bp_kernels.hip", "fp_kernels.hip", "fft_kernels.hip",
            "learn_kernels.hip"]
 
 HIPCC_FLAGS = [

@@ -24,7 +24,7 @@
 // of 1025 to 2048 samples, the Feldkamp pre-filter's case) that keeps each
 // pass in registers and fuses the loads, the spectrum product and the stores
 // into the passes.
-#include "fdk_internal.h"
+#include "learn_internal.h"
 
 namespace fdk {
 

@@ -18,7 +18,7 @@
 //   large terms).
 // wgrad kernels: per-block partial sums over a strided set of rows, then a
 //   fixed-order reduction over the blocks (deterministic).
-#include "fdk_internal.h"
+#include "learn_internal.h"
 
 #include <algorithm>
 
