@@ -132,6 +132,15 @@ hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
 // exact, independent of the order of the atomics.
 constexpr int kFpTile = 16;
 
+// x rounded to the nearest integer, ties towards +infinity (one instruction)
+__device__ __forceinline__ int cvt_nearest(float x)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+template <bool ALONG_Y>
 __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
 {
     extern __shared__ int tile[];  // A.fp_tile entries
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
     // other, and the 64 lanes of an atomic instruction hit 64 distinct
     // places (transverse neighbours ~2 px apart, z neighbours ~2 rows).
     const int tt = threadIdx.x & 15, zz = threadIdx.x >> 4;
-    const bool along_y = A.y_fastest != 0;
+    constexpr bool along_y = ALONG_Y;  // == (A.y_fastest != 0)
     const int x = along_y ? bx0 + tt : bx0;  // first voxel of the thread's line
     const int y = along_y ? by0 : by0 + tt;
     const int z = A.z_first + zl0 + zz;
@@ -241,12 +250,11 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
             for (int e = threadIdx.x; e < TW * TH; e += 256) tile[e] = 0;
             __syncthreads();
         }
-        // (u'w, v'w, w) of each voxel of the line, rounded exactly as the
-        // fused backprojection rounds them (x term, then y, then z), so that
-        // both operators see the same coordinates for every pair
-        const int last = TW * TH - TW - 2;
-#pragma unroll
-        for (int i = 0; i < kFpTile; ++i) {
+        // (u'w, v'w, w) of voxel i of the line, rounded exactly as the fused
+        // backprojection rounds them (x term, then y, then z), so that both
+        // operators see the same coordinates for every pair; then the
+        // fractions, the clamped tap indices and the weighted value r^2 x
+        auto voxel = [&](int i, float& au, float& av, int& iu, int& iv, float& s) {
             const float xi = along_y ? xp : xp + (float)i;
             const float yi = along_y ? yp + (float)i : yp;
             const float uw = fmaf(zp, m[2], fmaf(m[1], yi, fmaf(m[0], xi, m[3])));
@@ -255,22 +263,44 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
             const float r = __builtin_amdgcn_rcpf(w);
             const float u = uw * r;
             const float v = vw * r;
-            const float au = __builtin_amdgcn_fractf(u);
-            const float av = __builtin_amdgcn_fractf(v);
-            const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
-            const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
-            const float s = val[i] * (r * r);
-            const float b = s * av;
-            const float a = s - b;
-            const float tr = a * au, br = b * au;
-            if (use_lds) {
-                // inside the tile by construction; the clamp only guards it
-                const int l = min(max((iv - V0) * TW + (iu - U0), 0), last);
-                atomicAdd(&tile[l], (int)rintf((a - tr) * S));
-                atomicAdd(&tile[l + 1], (int)rintf(tr * S));
-                atomicAdd(&tile[l + TW], (int)rintf((b - br) * S));
-                atomicAdd(&tile[l + TW + 1], (int)rintf(br * S));
-            } else {
+            au = __builtin_amdgcn_fractf(u);
+            av = __builtin_amdgcn_fractf(v);
+            iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
+            iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
+            s = val[i] * (r * r);
+        };
+        if (use_lds) {
+            // tile index of tap (iu, iv): iv TW + iu - (V0 TW + U0); inside the
+            // tile by construction, the clamp only guards it
+            const int base = -(V0 * TW + U0);
+            const int last = TW * TH - TW - 2;
+#pragma unroll
+            for (int i = 0; i < kFpTile; ++i) {
+                float au, av, s;
+                int iu, iv;
+                voxel(i, au, av, iu, iv, s);
+                // in units of 1/S (exact: S is a power of two), rounded to the
+                // nearest integer, ties up (the same error bound as any
+                // round-to-nearest)
+                s *= S;
+                const float b = s * av;
+                const float a = s - b;
+                const float tr = a * au, br = b * au;
+                const int l = min(max(mad_i24(iv, TW, iu) + base, 0), last);
+                atomicAdd(&tile[l], cvt_nearest(a - tr));
+                atomicAdd(&tile[l + 1], cvt_nearest(tr));
+                atomicAdd(&tile[l + TW], cvt_nearest(b - br));
+                atomicAdd(&tile[l + TW + 1], cvt_nearest(br));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kFpTile; ++i) {
+                float au, av, s;
+                int iu, iv;
+                voxel(i, au, av, iu, iv, s);
+                const float b = s * av;
+                const float a = s - b;
+                const float tr = a * au, br = b * au;
                 const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
                 __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
                 __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
@@ -298,7 +328,11 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
 hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s)
 {
     dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
-    hipLaunchKernelGGL(fp_lds_kernel, grid, dim3(256), (size_t)a.fp_tile * sizeof(int), s, a);
+    const size_t lds = (size_t)a.fp_tile * sizeof(int);
+    if (a.y_fastest)
+        hipLaunchKernelGGL(fp_lds_kernel<true>, grid, dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL(fp_lds_kernel<false>, grid, dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
