@@ -73,37 +73,54 @@ __device__ __forceinline__ E diff2_elem(TT t, E d, E c, E b, E a)
     return from_f(t, (to_f(t, d) - to_f(t, c)) - (to_f(t, b) - to_f(t, a)));
 }
 
+// One thread per column and kStageRows consecutive rows of a staged plane:
+// the padded pixels of row r + 1 (and column c + 1 for the quad layouts)
+// carry over to the next row, so every input pixel is read once per layout
+// element column, and the blocks are few enough to stream.
+constexpr int kStageRows = 8;
+
 template <typename TT, int LAYOUT>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs a)
 {
     using E = typename TT::elem;
     const int col = blockIdx.x * 256 + threadIdx.x;
-    const int row = blockIdx.y;
+    const int row0 = blockIdx.y * kStageRows;
     const int view = blockIdx.z;
     if (col >= a.Wp) return;
     const E* src = (const E*)a.src + (size_t)view * a.H * a.W;
-    const size_t e = ((size_t)view * a.Hp + row) * a.Wp + col;
     E* dst = (E*)a.dst;
-    if (LAYOUT == kRows) {
-        dst[e] = staged_pixel(a, src, row, col);
-    } else if (LAYOUT == kPairs) {
-        E v[2] = {staged_pixel(a, src, row, col), staged_pixel(a, src, row + 1, col)};
-        __builtin_memcpy(dst + 2 * e, v, sizeof(v));
-    } else if (LAYOUT == kDPairs) {
-        const E p0 = staged_pixel(a, src, row, col), p1 = staged_pixel(a, src, row + 1, col);
-        E v[2] = {p0, diff_elem(TT{}, p1, p0)};
-        __builtin_memcpy(dst + 2 * e, v, sizeof(v));
-    } else if (LAYOUT == kDQuads) {
-        const E p00 = staged_pixel(a, src, row, col), p01 = staged_pixel(a, src, row, col + 1);
-        const E p10 = staged_pixel(a, src, row + 1, col);
-        const E p11 = staged_pixel(a, src, row + 1, col + 1);
-        E v[4] = {p00, diff_elem(TT{}, p10, p00), diff_elem(TT{}, p01, p00),
-                  diff2_elem(TT{}, p11, p01, p10, p00)};
-        __builtin_memcpy(dst + 4 * e, v, sizeof(v));
-    } else {
-        E v[4] = {staged_pixel(a, src, row, col), staged_pixel(a, src, row, col + 1),
-                  staged_pixel(a, src, row + 1, col), staged_pixel(a, src, row + 1, col + 1)};
-        __builtin_memcpy(dst + 4 * e, v, sizeof(v));
+    const int rows = min(kStageRows, a.Hp - row0);
+    // pixels (row, col) and (row, col + 1) of the current row
+    E p0 = staged_pixel(a, src, row0, col);
+    E q0 = (LAYOUT == kQuads || LAYOUT == kDQuads) ? staged_pixel(a, src, row0, col + 1) : E(0);
+    for (int k = 0; k < rows; ++k) {
+        const int row = row0 + k;
+        const size_t e = ((size_t)view * a.Hp + row) * a.Wp + col;
+        if (LAYOUT == kRows) {
+            dst[e] = p0;
+            if (k + 1 < rows) p0 = staged_pixel(a, src, row + 1, col);
+            continue;
+        }
+        const E p1 = staged_pixel(a, src, row + 1, col);
+        if (LAYOUT == kPairs) {
+            E v[2] = {p0, p1};
+            __builtin_memcpy(dst + 2 * e, v, sizeof(v));
+        } else if (LAYOUT == kDPairs) {
+            E v[2] = {p0, diff_elem(TT{}, p1, p0)};
+            __builtin_memcpy(dst + 2 * e, v, sizeof(v));
+        } else {
+            const E q1 = staged_pixel(a, src, row + 1, col + 1);
+            if (LAYOUT == kDQuads) {
+                E v[4] = {p0, diff_elem(TT{}, p1, p0), diff_elem(TT{}, q0, p0),
+                          diff2_elem(TT{}, q1, q0, p1, p0)};
+                __builtin_memcpy(dst + 4 * e, v, sizeof(v));
+            } else {
+                E v[4] = {p0, q0, p1, q1};
+                __builtin_memcpy(dst + 4 * e, v, sizeof(v));
+            }
+            q0 = q1;
+        }
+        p0 = p1;
     }
 }
 
@@ -124,7 +141,7 @@ static void launch_stage_t(const StageArgs& a, dim3 grid, hipStream_t s)
 
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s)
 {
-    dim3 grid((a.Wp + 255) / 256, a.Hp, a.count);
+    dim3 grid((a.Wp + 255) / 256, (a.Hp + kStageRows - 1) / kStageRows, a.count);
     if (storage == kF32)
         launch_stage_t<TF32>(a, grid, s);
     else if (storage == kF16)
