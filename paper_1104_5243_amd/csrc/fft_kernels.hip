@@ -20,10 +20,10 @@
 // large terms), rounded once to FP32 on output.
 //
 // Two kernels run the convolution: a general one for any L (its passes go
-// through LDS, pairs of radix-4 stages at a time), and one for L = 4096 (rows
-// of 1025 to 2048 samples, the Feldkamp pre-filter's case) that keeps each
-// pass in registers and fuses the loads, the spectrum product and the stores
-// into the passes.
+// through LDS, pairs of radix-4 stages at a time), and one for L = 4096 that
+// keeps each pass in registers and fuses the loads, the spectrum product and
+// the stores into the passes.  The host takes L = 4096 for rows of 513 to
+// 2048 samples (the Feldkamp pre-filter's 1248, the learned filter's 624).
 #include "learn_internal.h"
 
 namespace fdk {

@@ -168,7 +168,7 @@ def test_conv_long_forward_wgrad(env, W, rows):
 
 @pytest.mark.parametrize("W,rows", [(1300, 5), (2048, 2)])
 def test_conv_long_register_fft(env, W, rows):
-    """Rows of 1025..2048 samples take the L = 4096 FFT kernel that keeps
+    """Rows of 1025..2048 samples (like those of 513..1024) take the L = 4096 FFT kernel that keeps
     its passes in registers: forward with bias and accumulation, and the
     transposed call.  The adjoint of the correlation with taps w at offset
     pad is the correlation with the reversed taps at offset K - 1 - pad."""
