@@ -193,12 +193,9 @@ int fdk_conv_rows_wgrad(float* dweight, float* dbias, const float* dout, const f
         X.W = W;
         X.K = K;
         X.pad = pad;
-        X.L = 4;
-        X.log2L = 2;
-        while (X.L < K) {
-            X.L <<= 1;
-            ++X.log2L;
-        }
+        X.L = xcorr_length(K);
+        X.log2L = 0;
+        while ((1 << X.log2L) < X.L) ++X.log2L;
         X.blocks = std::max(1, std::min(kXcorrBlocks, (rows + 1) / 2));
         X.tw = (double2*)workspace;
         X.total = X.tw + kFftMax;

@@ -567,6 +567,30 @@ __device__ __forceinline__ void exchange(double* x, double2 (&v)[4][4], int t)
         for (int b = 0; b < 4; ++b) v[q][b].y = x[qx(posn<PR>(t, q, b))];
 }
 
+// Forward transform (L = 4096) of the complex row whose element p < W is
+// load(p) (zero from W on; W <= 2048) into v, thread t ending with the
+// elements 16 t + 4 q + b of the transform's output.  Starts with a barrier:
+// the buffer's previous reads may follow any pattern.
+template <typename Load>
+__device__ __forceinline__ void forward4096(double2 (&v)[4][4], double* x, const Roots16& c,
+                                            const double2* __restrict__ tw, int t, int W,
+                                            Load load)
+{
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int p = pos1(t, q, b);
+            v[q][b] = p < W ? load(p) : double2{0.0, 0.0};
+        }
+    r16_fwd<true, false>(v, t, c, tw);
+    __syncthreads();
+    exchange<1, 2>(x, v, t);
+    r16_fwd<false, false>(v, 16 * (t & 15), c, tw);
+    exchange<2, 3>(x, v, t);
+    r16_fwd<false, true>(v, 0, c, tw);
+}
+
 // Rows 2b and 2b + 1 (if any) of the call; a.L == 4096.  Three waves per
 // SIMD (168 VGPRs, a few spilled): 6.1 ms for fdk512's pre-filter, against
 // 7.6 ms at two waves and 7.9 ms at four (128 VGPRs, 42 spilled).
@@ -681,13 +705,62 @@ __global__ __launch_bounds__(kFftThreads) void fft_xcorr_partial_kernel(FftXcorr
     }
 }
 
+// L = 4096: the forward transforms run on registers as in the convolution
+// above (Z_x held while Z_d is formed: two waves per SIMD), and the block's
+// sums sit in part[b] in the order the registers hold them (element
+// 16 t + k of the transform at k * 256 + t, lane-contiguous).
+__global__ __launch_bounds__(kF16Threads, 2) void fft_xcorr4096_partial_kernel(FftXcorrArgs a)
+{
+    __shared__ double x[kF16Lds];
+    __shared__ double red[kF16Threads];
+    const int t = threadIdx.x;
+    const double2* __restrict__ tw = a.tw;
+    const Roots16 c = roots16(tw);
+    double2* S = a.part + (size_t)blockIdx.x * kFftMax;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) S[k * kF16Threads + t] = {0.0, 0.0};
+    double accb = 0.0;
+    const int pairs = (a.rows + 1) / 2;
+    for (int q = blockIdx.x; q < pairs; q += gridDim.x) {
+        const int r0 = 2 * q, r1 = r0 + 1;
+        const bool two = r1 < a.rows;
+        const float* x0 = a.in + (size_t)r0 * a.W;
+        const float* d0 = a.dout + (size_t)r0 * a.W;
+        double2 zx[4][4], zd[4][4];
+        forward4096(zx, x, c, tw, t, a.W, [&](int p) {
+            return double2{(double)x0[p], two ? (double)x0[a.W + p] : 0.0};
+        });
+        forward4096(zd, x, c, tw, t, a.W, [&](int p) {
+            const double2 d = {(double)d0[p], two ? (double)d0[a.W + p] : 0.0};
+            accb += d.x + d.y;
+            return d;
+        });
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                double2* s = S + (4 * qq + b) * kF16Threads + t;
+                *s = cadd(*s, cmulc(zx[qq][b], zd[qq][b]));
+            }
+    }
+    red[t] = accb;
+    __syncthreads();
+    if (t == 0) {
+        double sb = 0.0;
+        for (int k = 0; k < kF16Threads; ++k) sb += red[k];
+        a.bpart[blockIdx.x] = sb;
+    }
+}
+
 // total[p] = sum over the blocks (in block order) of part[b][p]
 __global__ __launch_bounds__(256) void fft_xcorr_sum_kernel(FftXcorrArgs a)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= a.L) return;
+    // the L = 4096 partial sums are in register order
+    const int src = a.L == kFftMax ? (p & 15) * kF16Threads + (p >> 4) : p;
     double2 s = {0.0, 0.0};
-    for (int b = 0; b < a.blocks; ++b) s = cadd(s, a.part[(size_t)b * a.L + p]);
+    for (int b = 0; b < a.blocks; ++b) s = cadd(s, a.part[(size_t)b * a.L + src]);
     a.total[p] = s;
 }
 
@@ -711,11 +784,18 @@ __global__ __launch_bounds__(kFftThreads) void fft_xcorr_final_kernel(FftXcorrAr
     }
 }
 
+int xcorr_length(int K)
+{
+    int L = 4;
+    while (L < K) L <<= 1;
+    // rows of 513..1024 samples take the register-resident L = 4096 kernel
+    return L == kFftMax / 2 ? kFftMax : L;
+}
+
 size_t fft_xcorr_workspace(int K)
 {
     if (K < 1 || !(K & 1) || K > kFftMax - 1) return 0;
-    int L = 4;
-    while (L < K) L <<= 1;
+    const int L = xcorr_length(K);
     return ((size_t)kFftMax + L + (size_t)kXcorrBlocks * L) * sizeof(double2) +
            (size_t)kXcorrBlocks * sizeof(double);
 }
@@ -725,8 +805,14 @@ hipError_t launch_fft_xcorr(const FftXcorrArgs& a, hipStream_t s)
     hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)2 * (a.L + a.L / 8) * sizeof(double2);
-    hipLaunchKernelGGL(fft_xcorr_partial_kernel, dim3(a.blocks), dim3(kFftThreads), lds, s, a);
+    if (a.L == kFftMax) {
+        hipLaunchKernelGGL(fft_xcorr4096_partial_kernel, dim3(a.blocks), dim3(kF16Threads), 0, s,
+                           a);
+    } else {
+        const size_t lds = (size_t)2 * (a.L + a.L / 8) * sizeof(double2);
+        hipLaunchKernelGGL(fft_xcorr_partial_kernel, dim3(a.blocks), dim3(kFftThreads), lds, s,
+                           a);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fft_xcorr_sum_kernel, dim3((a.L + 255) / 256), dim3(256), 0, s, a);

@@ -54,7 +54,9 @@ struct FftXcorrArgs {
     double2* part;        // blocks x L: the blocks' cross-spectrum sums
 };
 constexpr int kXcorrBlocks = 512;
-// workspace bytes of the FFT path for K taps (0 if K is not odd or too long)
+// transform length of the FFT path for K taps, and its workspace bytes (0 if
+// K is not odd or too long)
+int xcorr_length(int K);
 size_t fft_xcorr_workspace(int K);
 hipError_t launch_fft_xcorr(const FftXcorrArgs& a, hipStream_t s);
 
