@@ -88,3 +88,43 @@ def test_random_case(env, seed):
     tol = 1e-5 * max(1.0, math.sqrt(496.0 / V)) if c["storage"] == "f32" else 1e-3
     print(f"  relRMSE {err:.3e} (tolerance {tol:.1e})", flush=True)
     assert err <= tol
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_forward_case(env, seed):
+    """The forward projector on the same random scans, of a smooth random
+    volume: against the oracle's transpose (2e-5, the tolerance of smooth
+    inputs), and the adjoint identity <B p, x> = <p, F x> between the two
+    GPU operators."""
+    torch, fdk, dev = env
+    c = _case(seed, ["dpairs"])
+    g, N, V = c["geom"], c["N"], c["geom"].n_views
+    rng = np.random.default_rng(30_000 + seed)
+    grid = np.arange(N, dtype=np.float64)
+    x3 = np.zeros((N, N, N))
+    for _ in range(3):
+        f = rng.uniform(0.0, 0.4, 3)
+        x3 += rng.normal() * np.cos(f[0] * grid[None, None, :] + f[1] * grid[None, :, None]
+                                    + f[2] * grid[:, None, None] + rng.uniform(0, 2 * math.pi))
+    x3 = x3.astype(np.float32)
+    print(f"case {seed}: N={N} V={V} {g.W}x{g.H}", flush=True)
+    vol_d = torch.from_numpy(x3).to(dev)
+    fp = torch.zeros(V, g.H, g.W, device=dev)
+    fdk.forward_project(fp, vol_d, g.P, c["vs"], c["origin"])
+    proj_d = torch.from_numpy(c["proj"]).to(dev)
+    bp = torch.zeros(N, N, N, device=dev)
+    fdk.backproject(bp, proj_d, g.P, c["vs"], c["origin"])
+    torch.cuda.synchronize()
+    ref = oracle.forward_project(x3, g.P, g.H, g.W, c["vs"], c["origin"])
+    got = fp.cpu().numpy()
+    if not np.any(ref):
+        assert not np.any(got)
+        return
+    err = oracle.rel_rmse(got, ref)
+    lhs = float(np.dot(bp.cpu().numpy().ravel().astype(np.float64), x3.ravel()))
+    rhs = float(np.dot(c["proj"].ravel().astype(np.float64), got.ravel()))
+    scale = float(np.linalg.norm(bp.cpu().numpy()) * np.linalg.norm(x3))
+    print(f"  relRMSE {err:.3e}; adjoint |lhs - rhs| / scale {abs(lhs - rhs) / scale:.2e}",
+          flush=True)
+    assert err <= 2e-5
+    assert abs(lhs - rhs) <= 1e-5 * scale
