@@ -21,6 +21,7 @@
 #include "learn_internal.h"
 
 #include <algorithm>
+#include <cstdint>
 
 namespace fdk {
 
@@ -555,11 +556,58 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
     }
 }
 
+// One input channel with W a multiple of 4: a thread computes 4 consecutive
+// positions from its KT + 3 taps (read straight from global memory, shared
+// with its neighbours through the L1) and writes each output channel with
+// one 16-byte store (4-byte stores measured 0.98 ms against 0.56 ms for the
+// 32 channels of 128^3 x 62 views of 624-sample rows).
+template <int COUT, int KT>
+__global__ __launch_bounds__(256) void conv_narrow1x4_kernel(LearnConvArgs a)
+{
+    const int row = blockIdx.y;
+    const int j = (blockIdx.x * 256 + threadIdx.x) * 4;
+    if (j >= a.W) return;
+    const float* in = a.in + (size_t)row * a.W;
+    float* out = a.out + (size_t)row * COUT * a.W + j;
+    float xv[KT + 3];
+#pragma unroll
+    for (int t = 0; t < KT + 3; ++t) {
+        const int p = j + t - a.pad;
+        xv[t] = (p >= 0 && p < a.W) ? in[p] : 0.0f;
+    }
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) {
+        // the values this channel's outputs hold (mask, accumulate)
+        const float4 old = (a.mask || a.accumulate) ? *(const float4*)(out + (size_t)co * a.W)
+                                                    : float4{0.0f, 0.0f, 0.0f, 0.0f};
+        const float b = a.bias ? a.bias[co] : 0.0f;
+        float acc[4] = {b, b, b, b};
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+            const float w = conv_weight(a, co, 0, t);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = fmaf(w, xv[q + t], acc[q]);
+        }
+        const float ov[4] = {old.x, old.y, old.z, old.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (a.accumulate) acc[q] += ov[q];
+            if (a.relu) acc[q] = fmaxf(acc[q], 0.0f);
+            if (a.mask) acc[q] = ov[q] > 0.0f ? acc[q] : 0.0f;
+        }
+        *(float4*)(out + (size_t)co * a.W) = float4{acc[0], acc[1], acc[2], acc[3]};
+    }
+}
+
 hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s)
 {
     if (a.K == 9 && ((a.cin == 1 && a.cout == 32) || (a.cin == 32 && a.cout == 1))) {
+        // 16-byte stores need W a multiple of 4 and a 16-byte aligned output
         dim3 grid((a.W + 255) / 256, a.rows);
-        if (a.cin == 1)
+        if (a.cin == 1 && (a.W & 3) == 0 && ((uintptr_t)a.out & 15) == 0)
+            hipLaunchKernelGGL((conv_narrow1x4_kernel<32, 9>), dim3((a.W + 1023) / 1024, a.rows),
+                               dim3(256), 0, s, a);
+        else if (a.cin == 1)
             hipLaunchKernelGGL((conv_narrow_kernel<1, 32, 9>), grid, dim3(256), 0, s, a);
         else
             hipLaunchKernelGGL((conv_narrow_kernel<32, 1, 9>), grid, dim3(256), 0, s, a);

@@ -35,7 +35,7 @@ def rel(a, b):
 @pytest.mark.parametrize("cin,cout,W,rows,relu", [(1, 32, 37, 5, True), (32, 32, 64, 3, True),
                                                   (32, 1, 70, 4, False), (3, 5, 1, 2, False),
                                                   (1, 32, 300, 3, True), (32, 1, 513, 2, False),
-                                                  (4, 8, 130, 3, True)])
+                                                  (4, 8, 130, 3, True), (32, 1, 1028, 2, False)])
 def test_conv_short_forward_adjoint_wgrad(env, cin, cout, W, rows, relu):
     torch, fdk, GL, dev = env
     rng = np.random.default_rng(cin * 100 + cout)
