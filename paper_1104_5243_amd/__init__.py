@@ -32,7 +32,7 @@ EXPORTS = (
     "fdk_prefilter", "fdk_conv_rows", "fdk_conv_rows_wgrad_workspace", "fdk_conv_rows_wgrad",
     "fdk_scale_groups", "fdk_group_dot", "fdk_relu_backward", "fdk_matvec", "fdk_adam", "fdk_mse",
     "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
-    "fdk_set_layout", "fdk_release", "fdk_last_error", "fdk_version",
+    "fdk_set_layout", "fdk_set_row_clamp", "fdk_release", "fdk_last_error", "fdk_version",
 )
 
 _lib = None
@@ -80,6 +80,7 @@ def lib():
         L.fdk_profile_begin.argtypes = []
         L.fdk_profile_end.argtypes = [dp, ctypes.POINTER(ctypes.c_int)]
         L.fdk_set_batch.argtypes = [i]
+        L.fdk_set_row_clamp.argtypes = [i]
         L.fdk_release.argtypes = []
         L.fdk_last_error.argtypes = []
         L.fdk_last_error.restype = ctypes.c_char_p
@@ -387,6 +388,15 @@ def set_layout(layout) -> str:
     code = -1 if layout is None else LAYOUTS[layout]
     got = _check(lib().fdk_set_layout(code))
     return next(k for k, v in LAYOUTS.items() if v == got)
+
+
+def set_row_clamp(clamp=None) -> bool:
+    """Whether the fused backprojection clamps every tap row into the staged
+    plane (True) or, for FP16/BF16 storage, leaves rows outside it to the
+    buffer's range check where the geometry allows (False, the default);
+    None reads it back.  Results are bit-identical either way."""
+    code = -1 if clamp is None else (1 if clamp else 0)
+    return _check(lib().fdk_set_row_clamp(code)) == 1
 
 
 def release():

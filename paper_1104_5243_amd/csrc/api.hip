@@ -139,6 +139,13 @@ int g_fp_lds = []() {
     const char* e = std::getenv("FDK_FP_LDS");
     return (e && !std::strcmp(e, "0")) ? 0 : 1;
 }();
+// backprojection taps of rows outside the staged plane left to the buffer's
+// range check where the geometry allows it (FDK_ROWS_FREE=0 in the
+// environment always clamps v)
+std::atomic<int> g_rows_free = []() {
+    const char* e = std::getenv("FDK_ROWS_FREE");
+    return (e && !std::strcmp(e, "0")) ? 0 : 1;
+}();
 constexpr size_t kMaxStagingBytes = size_t(8) << 30;
 
 // ---- validation -----------------------------------------------------------
@@ -198,6 +205,27 @@ bool needs_wcheck(const double Q[12], double c)
         wmax = std::fmax(wmax, std::fabs(w));
     }
     return !(wmin > 1e-4 * wmax);
+}
+
+// True if every voxel of the centred box [-c, c]^3 has w > 0 and |v'| <=
+// vlim.  Then the tap row of each voxel, left unclamped, lies within vlim
+// (plus the centring) rows of the staged plane, so its 32-bit byte offset
+// cannot wrap around into the plane, and a row outside the plane reads as
+// zero through the buffer's range check: the kernel may skip the clamp of v.
+// (v' is a linear-fractional function of the voxel position; with w > 0 on
+// the box its extremes are at the box's corners.)
+bool rows_bounded(const double Q[12], double c, double vlim)
+{
+    double wmin = INFINITY, wmax = 0.0, vmax = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+        double x = (corner & 1) ? c : -c, y = (corner & 2) ? c : -c, z = (corner & 4) ? c : -c;
+        double w = Q[8] * x + Q[9] * y + Q[10] * z + Q[11];
+        double vw = Q[4] * x + Q[5] * y + Q[6] * z + Q[7];
+        wmin = std::fmin(wmin, w);
+        wmax = std::fmax(wmax, std::fabs(w));
+        vmax = std::fmax(vmax, std::fabs(vw / w));
+    }
+    return wmin > 1e-4 * wmax && vmax <= vlim;
 }
 
 // Unit direction from the volume centre (index frame) towards the source:
@@ -264,14 +292,17 @@ void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long l
 }
 
 // Fold the matrices of views [v0, v0+cnt) into out (cnt x 12 floats);
-// returns whether some voxel may have w <= 0, and sets the workgroup order
-// from the batch's mean ray direction.
+// returns whether some voxel may have w <= 0, sets *rows_free to whether
+// every view passes rows_bounded(vlim) (vlim <= 0: never), and sets the
+// workgroup order from the batch's mean ray direction.
 bool fold_batch(FusedArgs& A, float* out, const double* P, const float* view_scale, int v0,
-                int cnt, int N, float voxel_size, const float* origin, int H, int W)
+                int cnt, int N, float voxel_size, const float* origin, int H, int W,
+                double vlim, bool* rows_free)
 {
     const int ku = (W - 1) / 2, kv = (H - 1) / 2;
     const double c = 0.5 * (N - 1);
     bool wcheck = false;
+    *rows_free = vlim > 0.0;
     double ray[3] = {0.0, 0.0, 0.0};
     A.count = cnt;
     for (int j = 0; j < cnt; ++j) {
@@ -280,6 +311,7 @@ bool fold_batch(FusedArgs& A, float* out, const double* P, const float* view_sca
         double Q[12];
         fold_matrix(P + 12 * (size_t)(v0 + j), N, voxel_size, origin, ku, kv, lambda, Q);
         wcheck |= needs_wcheck(Q, c);
+        if (*rows_free) *rows_free = rows_bounded(Q, c, vlim);
         for (int k = 0; k < 12; ++k) out[12 * (size_t)j + k] = (float)Q[k];
         double d[3];
         source_direction(Q, d);
@@ -293,12 +325,12 @@ bool fold_batch(FusedArgs& A, float* out, const double* P, const float* view_sca
 // copied to the device (at `dev`, inside the staging buffer, so the
 // staging buffer's ordering protects it).
 struct Batches {
-    std::vector<int> v0, count, wcheck, y_fastest;
+    std::vector<int> v0, count, wcheck, rows_free, y_fastest;
 };
 
 int fold_and_upload(Staging* st, float* dev, const double* P, const float* view_scale,
                     int n_views, int batch, int N, float voxel_size, const float* origin, int H,
-                    int W, hipStream_t stream, Batches* B)
+                    int W, double vlim, hipStream_t stream, Batches* B)
 {
     hipError_t e;
     const size_t floats = 12 * (size_t)n_views;
@@ -327,11 +359,13 @@ int fold_and_upload(Staging* st, float* dev, const double* P, const float* view_
     FusedArgs A = {};
     for (int v0 = 0; v0 < n_views; v0 += batch) {
         const int cnt = std::min(batch, n_views - v0);
+        bool rows_free = false;
         const bool wcheck = fold_batch(A, st->host_mats + 12 * (size_t)v0, P, view_scale, v0,
-                                       cnt, N, voxel_size, origin, H, W);
+                                       cnt, N, voxel_size, origin, H, W, vlim, &rows_free);
         B->v0.push_back(v0);
         B->count.push_back(cnt);
         B->wcheck.push_back(wcheck ? 1 : 0);
+        B->rows_free.push_back(rows_free && !wcheck ? 1 : 0);
         B->y_fastest.push_back(A.y_fastest);
     }
     e = hipMemcpyAsync(dev, st->host_mats, floats * sizeof(float), hipMemcpyHostToDevice, stream);
@@ -374,9 +408,21 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     if (rc != FDK_OK) return rc;
     A.img = st->ptr;
     float* mats = (float*)((char*)st->ptr + planes);
+    // Rows outside the staged plane may be left to the buffer's range check
+    // (no clamp of v) when a tap row R satisfies |R| * Wp * elem < 2^31, so
+    // that its byte offset lands outside [0, plane_bytes) without wrapping:
+    // bound |v'| by a quarter of that, less the centring.  Only 16-bit
+    // storage, with one load per tap pair (not the rows layout, whose second
+    // load adds an offset): on fdk512 the unclamped FP16 kernel took 30.9
+    // against 31.5 ms, while the FP32 one, whatever the load schedule, was
+    // 2-15 % slower than with the clamp.
+    const double vlim = (layout == kRows || dtype == FDK_DTYPE_F32)
+                            ? 0.0
+                            : 0.25 * 2147483648.0 / ((double)Wp * (double)elem) -
+                                  (double)((H - 1) / 2 + kPad + 2);
     Batches B;
     rc = fold_and_upload(st, mats, P, view_scale, n_views, batch, N, voxel_size, origin, H, W,
-                         stream, &B);
+                         vlim, stream, &B);
     if (rc != FDK_OK) return rc;
 
     for (size_t b = 0; b < B.v0.size(); ++b) {
@@ -397,7 +443,8 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
         A.y_fastest = B.y_fastest[b];
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
-        e = launch_fused(A, dtype, layout, B.wcheck[b] != 0, stream);
+        e = launch_fused(A, dtype, layout, B.wcheck[b] != 0, g_rows_free && B.rows_free[b] != 0,
+                         stream);
         if (e != hipSuccess) return hip_fail(e, "backprojection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
     }
@@ -472,7 +519,7 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
     A.img = st->ptr;
     float* mats = (float*)((char*)st->ptr + planes);
     Batches B;
-    rc = fold_and_upload(st, mats, P, nullptr, n_views, batch, N, voxel_size, origin, H, W,
+    rc = fold_and_upload(st, mats, P, nullptr, n_views, batch, N, voxel_size, origin, H, W, 0.0,
                          stream, &B);
     if (rc != FDK_OK) return rc;
 
@@ -663,6 +710,15 @@ int fdk_set_layout(int layout)
         return fail(FDK_ERR_INVALID_ARG, "layout=%d is not one of 0..4", layout);
     g_layout = layout;
     return g_layout;
+}
+
+int fdk_set_row_clamp(int mode)
+{
+    g_err.clear();
+    if (mode == -1) return g_rows_free ? 0 : 1;
+    if (mode != 0 && mode != 1) return fail(FDK_ERR_INVALID_ARG, "mode=%d is not 0 or 1", mode);
+    g_rows_free = mode == 0 ? 1 : 0;
+    return mode;
 }
 
 int fdk_release(void)

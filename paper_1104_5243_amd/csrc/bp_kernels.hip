@@ -270,8 +270,11 @@ static_assert(kWaveX * kWaveY == 64, "a wave covers 64 columns");
 
 // One view's contribution to the fused_z voxels of this thread.  CLAMP
 // selects the clamped tap addressing (needed when some voxel of the wave
-// may project outside the zero border of the staged plane).
-template <typename TT, int LAYOUT, bool WCHECK, bool CLAMP>
+// may project outside the zero border of the staged plane); with VCLAMP
+// false only u is clamped, and a tap row outside the plane gives a byte
+// offset outside the buffer's range, which reads as zero (the host has
+// bounded the rows so that the offset cannot wrap into the plane).
+template <typename TT, int LAYOUT, bool WCHECK, bool CLAMP, bool VCLAMP>
 __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_float* m, float xp,
                                                 float yp, float zp0,
                                                 __amdgpu_buffer_rsrc_t rsrc,
@@ -308,7 +311,8 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_
             au[q] = __builtin_amdgcn_fractf(u);
             av[q] = __builtin_amdgcn_fractf(v);
             const int iu = cvt_floor(CLAMP ? __builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u) : u);
-            const int iv = cvt_floor(CLAMP ? __builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v) : v);
+            const int iv =
+                cvt_floor(CLAMP && VCLAMP ? __builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v) : v);
             const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * kElem + centre_bytes;
             if constexpr (kIsF32)
                 load_taps<LAYOUT>(TT{}, rsrc, off, row_bytes, tl[q], tr[q], bl[q], br[q]);
@@ -343,7 +347,7 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_
 #ifndef FDK_MIN_WAVES
 #define FDK_MIN_WAVES 8
 #endif
-template <typename TT, int LAYOUT, bool WCHECK>
+template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP>
 __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused_kernel(const FusedArgs A)
 {
     using E = typename TT::elem;
@@ -402,7 +406,7 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
         const const_float* m = mats + 12 * j;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
         if constexpr (WCHECK) {
-            accumulate_view<TT, LAYOUT, WCHECK, true>(A, m, xp, yp, zp0, rsrc, acc);
+            accumulate_view<TT, LAYOUT, WCHECK, true, true>(A, m, xp, yp, zp0, rsrc, acc);
         } else {
             const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
             const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
@@ -412,7 +416,7 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
             if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
                 __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
                 continue;
-            accumulate_view<TT, LAYOUT, false, true>(A, m, xp, yp, zp0, rsrc, acc);
+            accumulate_view<TT, LAYOUT, false, true, VCLAMP>(A, m, xp, yp, zp0, rsrc, acc);
         }
     }
 
@@ -426,38 +430,49 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
 }
 
 template <typename TT, int LAYOUT>
-static void launch_fused_t(const FusedArgs& a, bool wcheck, hipStream_t s)
+static void launch_fused_t(const FusedArgs& a, bool wcheck, bool rows_free, hipStream_t s)
 {
     dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
     if (wcheck)
-        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, true>), grid, dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false>), grid, dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, true, true>), grid, dim3(kThreads), 0, s,
+                           a);
+    else if constexpr (sizeof(typename TT::elem) == 2 && LAYOUT != kRows) {
+        if (rows_free)
+            hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, false>), grid, dim3(kThreads),
+                               0, s, a);
+        else
+            hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, true>), grid, dim3(kThreads),
+                               0, s, a);
+    } else
+        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, true>), grid, dim3(kThreads), 0, s,
+                           a);
 }
 
 template <typename TT>
-static void launch_fused_l(const FusedArgs& a, int layout, bool wcheck, hipStream_t s)
+static void launch_fused_l(const FusedArgs& a, int layout, bool wcheck, bool rows_free,
+                           hipStream_t s)
 {
     if (layout == kRows)
-        launch_fused_t<TT, kRows>(a, wcheck, s);
+        launch_fused_t<TT, kRows>(a, wcheck, false, s);
     else if (layout == kPairs)
-        launch_fused_t<TT, kPairs>(a, wcheck, s);
+        launch_fused_t<TT, kPairs>(a, wcheck, rows_free, s);
     else if (layout == kDPairs)
-        launch_fused_t<TT, kDPairs>(a, wcheck, s);
+        launch_fused_t<TT, kDPairs>(a, wcheck, rows_free, s);
     else if (layout == kDQuads)
-        launch_fused_t<TT, kDQuads>(a, wcheck, s);
+        launch_fused_t<TT, kDQuads>(a, wcheck, rows_free, s);
     else
-        launch_fused_t<TT, kQuads>(a, wcheck, s);
+        launch_fused_t<TT, kQuads>(a, wcheck, rows_free, s);
 }
 
-hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, hipStream_t s)
+hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, bool rows_free,
+                        hipStream_t s)
 {
     if (storage == kF32)
-        launch_fused_l<TF32>(a, layout, wcheck, s);
+        launch_fused_l<TF32>(a, layout, wcheck, rows_free, s);
     else if (storage == kF16)
-        launch_fused_l<TF16>(a, layout, wcheck, s);
+        launch_fused_l<TF16>(a, layout, wcheck, rows_free, s);
     else
-        launch_fused_l<TBF16>(a, layout, wcheck, s);
+        launch_fused_l<TBF16>(a, layout, wcheck, rows_free, s);
     return hipGetLastError();
 }
 

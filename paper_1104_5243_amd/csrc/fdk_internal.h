@@ -99,7 +99,10 @@ struct UnstageArgs {
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s);
-hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, hipStream_t s);
+// rows_free: v is not clamped (only with !wcheck and a single-load layout;
+// the host has bounded every tap row, see rows_bounded)
+hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, bool rows_free,
+                        hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, hipStream_t s);
 hipError_t launch_update_probe(float* a, size_t n, float s, hipStream_t st);
 hipError_t launch_zero(float* a, size_t n, hipStream_t st);

@@ -132,6 +132,19 @@ def test_layout_setting():
     assert L.fdk_set_layout(old) == old
 
 
+def test_row_clamp_setting():
+    L = fdk.lib()
+    old = L.fdk_set_row_clamp(-1)
+    assert old in (0, 1)
+    assert L.fdk_set_row_clamp(2) == fdk.FDK_ERR_INVALID_ARG
+    assert L.fdk_set_row_clamp(-2) == fdk.FDK_ERR_INVALID_ARG
+    assert fdk.set_row_clamp(True) is True
+    assert L.fdk_set_row_clamp(-1) == 1
+    assert fdk.set_row_clamp(False) is False
+    assert fdk.set_row_clamp(None) is False
+    assert L.fdk_set_row_clamp(old) == old
+
+
 C_PROGRAM = r"""
 #include <stdio.h>
 #include <string.h>

@@ -129,6 +129,39 @@ def test_every_layout_and_storage_parity_128(torch_dev, fdk_mod, stack, ref128, 
     assert err <= (FP32_TOL if dtype_name == "float32" else 1e-3)
 
 
+@pytest.mark.parametrize("layout", ["pairs", "dpairs", "dquads"])
+@pytest.mark.parametrize("dtype_name", ["float16", "bfloat16"])
+@pytest.mark.parametrize("shift_mm", [0.0, 150.0])
+def test_row_clamp_setting_is_bit_identical(torch_dev, fdk_mod, stack, layout, dtype_name,
+                                            shift_mm):
+    """Tap rows outside the staged plane read as zero whether they are clamped
+    into its zero border or left to the buffer's range check (16-bit storage):
+    the volumes are bit-identical.  With the volume raised by 150 mm most voxels project above
+    the detector in every view."""
+    torch, dev = torch_dev
+    geom, proj, proj_d = stack
+    vs, o = synth.volume_frame(128)
+    o = (o[0], o[1], o[2] + shift_mm)
+    old_layout, old_clamp = fdk_mod.set_layout(None), fdk_mod.set_row_clamp(None)
+    vols = []
+    try:
+        fdk_mod.set_layout(layout)
+        for clamp in (True, False):
+            fdk_mod.set_row_clamp(clamp)
+            vol = torch.zeros(128, 128, 128, device=dev)
+            st, scale = fdk_mod.to_storage(proj_d, getattr(torch, dtype_name))
+            fdk_mod.backproject(vol, st, geom.P, vs, o, view_scale=scale)
+            torch.cuda.synchronize()
+            vols.append(vol)
+    finally:
+        fdk_mod.set_layout(old_layout)
+        fdk_mod.set_row_clamp(old_clamp)
+    print(f"{layout} {dtype_name} shift {shift_mm}: nonzero {int((vols[0] != 0).sum())}",
+          flush=True)
+    assert torch.any(vols[0] != 0)
+    assert torch.equal(vols[0], vols[1])
+
+
 @pytest.mark.parametrize("split", [64, 100, 1])
 def test_views_split_over_calls_accumulate(torch_dev, fdk_mod, stack, split):
     torch, dev = torch_dev
