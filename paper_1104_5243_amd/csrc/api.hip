@@ -318,6 +318,13 @@ bool fold_batch(FusedArgs& A, float* out, const double* P, const float* view_sca
         for (int k = 0; k < 3; ++k) ray[k] += std::fabs(d[k]);
     }
     A.y_fastest = ray[1] > ray[0] ? 1 : 0;
+    // The kernels take the matrices in the batch's ray frame: column 0
+    // multiplies the transverse coordinate, column 1 the one along the
+    // rays (the workgroup order's fastest axis).  With rays along x, swap.
+    if (!A.y_fastest)
+        for (int j = 0; j < cnt; ++j)
+            for (int r = 0; r < 3; ++r)
+                std::swap(out[12 * (size_t)j + 4 * r], out[12 * (size_t)j + 4 * r + 1]);
     return wcheck;
 }
 

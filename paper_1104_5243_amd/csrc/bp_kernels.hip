@@ -274,9 +274,16 @@ static_assert(kWaveX * kWaveY == 64, "a wave covers 64 columns");
 // false only u is clamped, and a tap row outside the plane gives a byte
 // offset outside the buffer's range, which reads as zero (the host has
 // bounded the rows so that the offset cannot wrap into the plane).
+//
+// The matrices are in the batch's ray frame (column 0 transverse, column 1
+// along the rays).  The column base (u'w, v'w, w at z = 0) adds the
+// transverse term first and the ray term second (pt, pr: the thread's
+// coordinates on those axes), then each voxel its z term: the forward
+// projector, which walks the ray axis, rounds every pair's coordinates in
+// this same order.
 template <typename TT, int LAYOUT, bool WCHECK, bool CLAMP, bool VCLAMP>
-__device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_float* m, float xp,
-                                                float yp, float zp0,
+__device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_float* m, float pt,
+                                                float pr, float zp0,
                                                 __amdgpu_buffer_rsrc_t rsrc,
                                                 float (&acc)[fused_z(TT::id)])
 {
@@ -287,9 +294,9 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_
     const int Wp = A.Wp;
     const uint32_t row_bytes = (uint32_t)Wp * kElem;
     const uint32_t centre_bytes = (uint32_t)A.origin_off * kElem;
-    const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
-    const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
-    const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
+    const float bu = fmaf(m[1], pr, fmaf(m[0], pt, m[3]));
+    const float bv = fmaf(m[5], pr, fmaf(m[4], pt, m[7]));
+    const float bw = fmaf(m[9], pr, fmaf(m[8], pt, m[11]));
 #pragma unroll
     for (int g = 0; g < kFusedZ; g += kGroup) {
         float au[kGroup], av[kGroup], r2[kGroup];
@@ -383,6 +390,8 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     const float xp = (float)x - A.c;
     const float yp = (float)y - A.c;
     const float zp0 = (float)(A.z_first + zl0) - A.c;
+    const float pt = A.y_fastest ? xp : yp;  // transverse and ray coordinates
+    const float pr = A.y_fastest ? yp : xp;
 
     // Lanes 0..7 hold the corners of the wave's kWaveX x kWaveY x kFusedZ
     // voxel box.  With w > 0 on the box, every voxel projects inside the
@@ -393,6 +402,7 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
     const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
     const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
+    const float ctp = A.y_fastest ? cxp : cyp, crp = A.y_fastest ? cyp : cxp;
     const bool corner_lane = lane < 8;
 
     float acc[kFusedZ];
@@ -406,17 +416,17 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
         const const_float* m = mats + 12 * j;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
         if constexpr (WCHECK) {
-            accumulate_view<TT, LAYOUT, WCHECK, true, true>(A, m, xp, yp, zp0, rsrc, acc);
+            accumulate_view<TT, LAYOUT, WCHECK, true, true>(A, m, pt, pr, zp0, rsrc, acc);
         } else {
-            const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
-            const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
-            const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
+            const float cu = fmaf(czp, m[2], fmaf(m[1], crp, fmaf(m[0], ctp, m[3])));
+            const float cv = fmaf(czp, m[6], fmaf(m[5], crp, fmaf(m[4], ctp, m[7])));
+            const float cw = fmaf(czp, m[10], fmaf(m[9], crp, fmaf(m[8], ctp, m[11])));
             const float cr = __builtin_amdgcn_rcpf(cw);
             const float u = cu * cr, v = cv * cr;
             if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
                 __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
                 continue;
-            accumulate_view<TT, LAYOUT, false, true, VCLAMP>(A, m, xp, yp, zp0, rsrc, acc);
+            accumulate_view<TT, LAYOUT, false, true, VCLAMP>(A, m, pt, pr, zp0, rsrc, acc);
         }
     }
 

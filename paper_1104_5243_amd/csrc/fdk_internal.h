@@ -65,7 +65,9 @@ struct FusedArgs {
     int tiles_x, tiles_y, zchunks;
     int xcd_remap;       // 1: spread consecutive tiles over XCD-local ranges
     int y_fastest;       // 1: consecutive workgroups step along y, else along x
-    const float* m;      // count x 12 folded matrices of this batch (device memory)
+    const float* m;      // count x 12 folded matrices of this batch (device memory), in
+                         // the ray frame: column 0 multiplies the transverse coordinate
+                         // (x if y_fastest, else y), column 1 the ray coordinate
     int fp_tile;         // forward projection: entries of a workgroup's LDS tile
 };
 

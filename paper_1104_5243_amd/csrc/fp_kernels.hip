@@ -41,6 +41,9 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
     const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
     const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
     const float czp = zp0 + ((lane & 4) ? (float)(kFpZ - 1) : 0.0f);
+    // transverse and ray coordinates (the matrices are in the ray frame)
+    const float ctp = A.y_fastest ? cxp : cyp, crp = A.y_fastest ? cyp : cxp;
+    const float pt = A.y_fastest ? xp : yp, pr = A.y_fastest ? yp : xp;
     const bool corner_lane = lane < 8;
 
     // the thread's voxel values (0 outside the volume)
@@ -62,18 +65,20 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
         const const_float* m = mats + 12 * j;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
         if constexpr (!WCHECK) {
-            const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
-            const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
-            const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
+            const float cu = fmaf(czp, m[2], fmaf(m[1], crp, fmaf(m[0], ctp, m[3])));
+            const float cv = fmaf(czp, m[6], fmaf(m[5], crp, fmaf(m[4], ctp, m[7])));
+            const float cw = fmaf(czp, m[10], fmaf(m[9], crp, fmaf(m[8], ctp, m[11])));
             const float cr = __builtin_amdgcn_rcpf(cw);
             const float u = cu * cr, v = cv * cr;
             if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
                 __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
                 continue;
         }
-        const float bu = fmaf(m[1], yp, fmaf(m[0], xp, m[3]));
-        const float bv = fmaf(m[5], yp, fmaf(m[4], xp, m[7]));
-        const float bw = fmaf(m[9], yp, fmaf(m[8], xp, m[11]));
+        // the column base in the backprojection's order: the transverse
+        // term first, then the ray term
+        const float bu = fmaf(m[1], pr, fmaf(m[0], pt, m[3]));
+        const float bv = fmaf(m[5], pr, fmaf(m[4], pt, m[7]));
+        const float bw = fmaf(m[9], pr, fmaf(m[8], pt, m[11]));
 #pragma unroll
         for (int i = 0; i < kFpZ; ++i) {
             const float zp = zp0 + (float)i;
@@ -140,11 +145,19 @@ __device__ __forceinline__ int cvt_nearest(float x)
     return r;
 }
 
+// waves per SIMD the registers are fitted to (up to 128 VGPRs).  Five 32 KiB
+// tiles would fit the 160 KiB of LDS of a CU, but fitting the kernel to 5
+// waves (96 VGPRs) spills: 256^3 x 248 views took 3.46 ms against 2.85 ms.
+#ifndef FDK_FP_WAVES
+#define FDK_FP_WAVES 4
+#endif
 template <bool ALONG_Y>
-__global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
+__global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedArgs A)
 {
-    extern __shared__ int tile[];  // A.fp_tile entries
-    __shared__ float wave_max[4];
+    // A.fp_tile tile entries at LDS address 0; the first 4 hold the wave
+    // maxima of the box's values before the first view
+    extern __shared__ int tile[];
+    float* wave_max = (float*)tile;
     int bid = blockIdx.x;
     if (A.xcd_remap) {
         const int per = gridDim.x >> 3;
@@ -178,6 +191,9 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
     const float cxp = (float)(bx0 + ((lane & 1) ? kFpTile - 1 : 0)) - A.c;
     const float cyp = (float)(by0 + ((lane & 2) ? kFpTile - 1 : 0)) - A.c;
     const float czp = (float)(A.z_first + zl0) - A.c + ((lane & 4) ? (float)(kFpZ - 1) : 0.0f);
+    // transverse and ray coordinates (the matrices are in the ray frame)
+    const float ctp = along_y ? cxp : cyp, crp = along_y ? cyp : cxp;
+    const float pt = along_y ? xp : yp, pr0 = along_y ? yp : xp;
     const bool corner_lane = lane < 8;
 
     float val[kFpTile];
@@ -198,6 +214,7 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
     __syncthreads();
     vmax = fmaxf(fmaxf(wave_max[0], wave_max[1]), fmaxf(wave_max[2], wave_max[3]));
     if (vmax == 0.0f) return;  // nothing to project (uniform over the block)
+    __syncthreads();           // every wave has read wave_max before the tile is zeroed
 
     const int Wp = A.Wp;
     const uint32_t row_bytes = (uint32_t)Wp * 4u;
@@ -210,9 +227,9 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
     for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
         const const_float* m = mats + 12 * j;
         const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
-        const float cu = fmaf(czp, m[2], fmaf(m[1], cyp, fmaf(m[0], cxp, m[3])));
-        const float cv = fmaf(czp, m[6], fmaf(m[5], cyp, fmaf(m[4], cxp, m[7])));
-        const float cw = fmaf(czp, m[10], fmaf(m[9], cyp, fmaf(m[8], cxp, m[11])));
+        const float cu = fmaf(czp, m[2], fmaf(m[1], crp, fmaf(m[0], ctp, m[3])));
+        const float cv = fmaf(czp, m[6], fmaf(m[5], crp, fmaf(m[4], ctp, m[7])));
+        const float cw = fmaf(czp, m[10], fmaf(m[9], crp, fmaf(m[8], ctp, m[11])));
         const float cr = __builtin_amdgcn_rcpf(cw);
         float umin = corner_lane ? cu * cr : INFINITY, umax = corner_lane ? cu * cr : -INFINITY;
         float vmin = corner_lane ? cv * cr : INFINITY, vmx = corner_lane ? cv * cr : -INFINITY;
@@ -251,34 +268,44 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
             __syncthreads();
         }
         // (u'w, v'w, w) of voxel i of the line, rounded exactly as the fused
-        // backprojection rounds them (x term, then y, then z), so that both
-        // operators see the same coordinates for every pair; then the
-        // fractions, the clamped tap indices and the weighted value r^2 x
-        auto voxel = [&](int i, float& au, float& av, int& iu, int& iv, float& s) {
-            const float xi = along_y ? xp : xp + (float)i;
-            const float yi = along_y ? yp + (float)i : yp;
-            const float uw = fmaf(zp, m[2], fmaf(m[1], yi, fmaf(m[0], xi, m[3])));
-            const float vw = fmaf(zp, m[6], fmaf(m[5], yi, fmaf(m[4], xi, m[7])));
-            const float w = fmaf(zp, m[10], fmaf(m[9], yi, fmaf(m[8], xi, m[11])));
+        // backprojection rounds them (the transverse axis's term, then the
+        // ray axis's, then z), so that both operators see the same
+        // coordinates for every pair; the transverse term is the line's
+        // constant.  Then the fractions, the tap indices of the coordinates
+        // clamped to [lo, hi], and the weighted value r^2 x.
+        const float tu = fmaf(m[0], pt, m[3]);
+        const float tv = fmaf(m[4], pt, m[7]);
+        const float tw = fmaf(m[8], pt, m[11]);
+        auto voxel = [&](int i, float lo_u, float hi_u, float lo_v, float hi_v, float& au,
+                         float& av, int& iu, int& iv, float& s) {
+            const float pr = pr0 + (float)i;
+            const float uw = fmaf(zp, m[2], fmaf(m[1], pr, tu));
+            const float vw = fmaf(zp, m[6], fmaf(m[5], pr, tv));
+            const float w = fmaf(zp, m[10], fmaf(m[9], pr, tw));
             const float r = __builtin_amdgcn_rcpf(w);
             const float u = uw * r;
             const float v = vw * r;
             au = __builtin_amdgcn_fractf(u);
             av = __builtin_amdgcn_fractf(v);
-            iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
-            iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
+            iu = cvt_floor(__builtin_amdgcn_fmed3f(u, lo_u, hi_u));
+            iv = cvt_floor(__builtin_amdgcn_fmed3f(v, lo_v, hi_v));
             s = val[i] * (r * r);
         };
         if (use_lds) {
-            // tile index of tap (iu, iv): iv TW + iu - (V0 TW + U0); inside the
-            // tile by construction, the clamp only guards it
+            // Tap (iu, iv) at tile index (iv - V0) TW + (iu - U0).  Clamping u
+            // to [U0, U1 - 0.5] and v to [V0, V1 - 0.5] keeps all four taps
+            // inside the tile; it changes no tap: the box projects inside
+            // [umin, umax] x [vmin, vmax], one pixel inside the tile, except
+            // where U0 = lo_u or U1 = hi_u + 1 (likewise v), and there it is
+            // the clamp to the padded plane's border that every path applies.
             const int base = -(V0 * TW + U0);
-            const int last = TW * TH - TW - 2;
+            const float cu0 = (float)U0, cu1 = (float)U1 - 0.5f;
+            const float cv0 = (float)V0, cv1 = (float)V1 - 0.5f;
 #pragma unroll
             for (int i = 0; i < kFpTile; ++i) {
                 float au, av, s;
                 int iu, iv;
-                voxel(i, au, av, iu, iv, s);
+                voxel(i, cu0, cu1, cv0, cv1, au, av, iu, iv, s);
                 // in units of 1/S (exact: S is a power of two), rounded to the
                 // nearest integer, ties up (the same error bound as any
                 // round-to-nearest)
@@ -286,18 +313,19 @@ __global__ __launch_bounds__(256) void fp_lds_kernel(const FusedArgs A)
                 const float b = s * av;
                 const float a = s - b;
                 const float tr = a * au, br = b * au;
-                const int l = min(max(mad_i24(iv, TW, iu) + base, 0), last);
-                atomicAdd(&tile[l], cvt_nearest(a - tr));
-                atomicAdd(&tile[l + 1], cvt_nearest(tr));
-                atomicAdd(&tile[l + TW], cvt_nearest(b - br));
-                atomicAdd(&tile[l + TW + 1], cvt_nearest(br));
+                int* t0 = tile + (mad_i24(iv, TW, iu) + base);
+                int* t1 = t0 + TW;
+                atomicAdd(t0, cvt_nearest(a - tr));
+                atomicAdd(t0 + 1, cvt_nearest(tr));
+                atomicAdd(t1, cvt_nearest(b - br));
+                atomicAdd(t1 + 1, cvt_nearest(br));
             }
         } else {
 #pragma unroll
             for (int i = 0; i < kFpTile; ++i) {
                 float au, av, s;
                 int iu, iv;
-                voxel(i, au, av, iu, iv, s);
+                voxel(i, A.lo_u, A.hi_u, A.lo_v, A.hi_v, au, av, iu, iv, s);
                 const float b = s * av;
                 const float a = s - b;
                 const float tr = a * au, br = b * au;
