@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
         const int j0 = (c - row * chunks_per_row) * C::kChunk;
         tile.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
     };
-    if (blockIdx.x < total_chunks) fetch(blockIdx.x);
+    if ((int)blockIdx.x < total_chunks) fetch(blockIdx.x);
     for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
         const int row = c / chunks_per_row;
         const int j0 = (c - row * chunks_per_row) * C::kChunk;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256, (WgradMfma<CIN, COUT, KT>::kMinWaves)) void wg
         dtile.fetch(a.dout + (size_t)row * COUT * a.W, a.W, j0);
         xtile.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
     };
-    if (blockIdx.x < total_chunks) fetch(blockIdx.x);
+    if ((int)blockIdx.x < total_chunks) fetch(blockIdx.x);
     for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
         __syncthreads();
         dtile.put(dy);
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(256) void wgrad_c1_kernel(LearnGradArgs a, int chun
         xtile.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0);
         dtile.fetch(a.dout + (size_t)row * a.W, a.W, j0 - (KT - 1 - a.pad));
     };
-    if (blockIdx.x < total_chunks) fetch(blockIdx.x);
+    if ((int)blockIdx.x < total_chunks) fetch(blockIdx.x);
     for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
         __syncthreads();
         xtile.put(xt);
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(LearnGradArgs a)
                     acc[q] += dot_f64(dy + co * kGradChunk, x + ci * span + t, n);
                 }
             }
-            if (threadIdx.x < a.cout) {
+            if ((int)threadIdx.x < a.cout) {
                 const float* d = dy + threadIdx.x * kGradChunk;
                 double s = 0.0;
                 for (int p = 0; p < n; ++p) s += (double)d[p];
@@ -709,7 +709,7 @@ __global__ __launch_bounds__(256) void wgrad_partial_kernel(LearnGradArgs a)
         const int e = threadIdx.x + 256 * q;
         if (e < nw) part[e] = acc[q];
     }
-    if (threadIdx.x < a.cout) part[nw + threadIdx.x] = accb;
+    if ((int)threadIdx.x < a.cout) part[nw + threadIdx.x] = accb;
 }
 
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(LearnGradArgs a, int nblocks)
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(1024) void group_dot_kernel(float* out, const float
     red[threadIdx.x] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[blockIdx.x] = (float)red[0];
@@ -943,7 +943,7 @@ __global__ __launch_bounds__(256) void mse_kernel(float* grad, double* part, con
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
