@@ -209,8 +209,8 @@ def bench_prefilter(args, torch, fdk, synth, dev):
         f"fdk512 pre-filter: {V} line-integral views of {W}x{H}, FP32 in/out, FP64 inside",
         {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
          "frac": round(ach / 78.6, 4), "traffic": None,
-         "kernel": ("fft_conv4096_kernel (FP64 FFT, L=4096, radix-16 passes in registers, "
-                    "two rows per transform)" if L == 4096 else
+         "kernel": ("fft_conv4096_real_kernel (FP64 FFT, L=4096, radix-16 passes in "
+                    "registers, two rows per transform, real Ram-Lak spectrum)" if L == 4096 else
                     f"fft_conv_kernel (FP64 FFT, L={L}, two rows per transform)"),
          "launches_per_step": launches // args.steps,
          "kernel_ms_per_step": round(kms / args.steps, 3)},
