@@ -433,9 +433,19 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     if (x < A.N && y < A.N) {
         const size_t slice = (size_t)A.N * A.N;
         float* out = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
+        if (zl0 + kFusedZ <= A.nz) {
+            // all the column's loads in flight together (a test per voxel
+            // would make the compiler wait for each before the next)
+            float old[kFusedZ];
 #pragma unroll
-        for (int i = 0; i < kFusedZ; ++i)
-            if (zl0 + i < A.nz) out[(size_t)i * slice] += acc[i];
+            for (int i = 0; i < kFusedZ; ++i) old[i] = out[(size_t)i * slice];
+#pragma unroll
+            for (int i = 0; i < kFusedZ; ++i) out[(size_t)i * slice] = old[i] + acc[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < kFusedZ; ++i)
+                if (zl0 + i < A.nz) out[(size_t)i * slice] += acc[i];
+        }
     }
 }
 

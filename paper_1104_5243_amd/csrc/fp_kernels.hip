@@ -199,13 +199,16 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     float val[kFpTile];
     const size_t slice = (size_t)A.N * A.N;
     const bool zin = zl0 + zz < A.nz;
-    const float* src = A.vol + (size_t)z * slice + (size_t)y * A.N + x;
-    const size_t step = along_y ? (size_t)A.N : 1;
+    // every lane reads an existing voxel (indices clamped into the volume)
+    // and keeps it only if it is its own: no test per load, so that the
+    // loads are in flight together
+    const float* src = A.vol + (size_t)min(z, A.z_first + A.nz - 1) * slice;
     float vmax = 0.0f;
 #pragma unroll
     for (int i = 0; i < kFpTile; ++i) {
         const int xi = along_y ? x : x + i, yi = along_y ? y + i : y;
-        val[i] = (zin && xi < A.N && yi < A.N) ? src[(size_t)i * step] : 0.0f;
+        const float v = src[(size_t)min(yi, A.N - 1) * A.N + min(xi, A.N - 1)];
+        val[i] = (zin && xi < A.N && yi < A.N) ? v : 0.0f;
         vmax = fmaxf(vmax, fabsf(val[i]));
     }
 #pragma unroll
