@@ -259,17 +259,18 @@ int fdk_set_layout(int layout);
 
 /*
  * Row clamping of the fused backprojection's taps (a tuning knob; results
- * are bit-identical either way).  A voxel's tap row outside the zero-padded
- * staged plane contributes zero (Section 3.2 part 3: samples outside the
- * detector are zero).  With 1 every tap row is clamped into the plane's
- * zero border.  With 0 (the default) a launch of FP16 or BF16 storage in
- * a single-load layout (not FDK_LAYOUT_ROWS) whose voxels all have w > 0
- * and tap rows within a bound the host derives from the plane's pitch (so
- * that a 32-bit byte offset cannot wrap) leaves such rows unclamped: their
- * offsets fall outside the plane's buffer range and the loads return zero
- * without touching memory; other launches, and FP32 storage (faster
- * clamped), clamp.  -1 reads the setting back.  Returns the setting or FDK_ERR_INVALID_ARG.  The environment
- * variable FDK_ROWS_FREE=0 sets the initial value to 1.
+ * are bit-identical either way).  A voxel's tap row outside the staged
+ * plane contributes zero (the zero-padded projections of Section 3.3).
+ * With 1 every tap row is clamped into the plane's zero border.  With 0
+ * (the default) a launch of FP16 or BF16 storage in a single-load layout
+ * (not FDK_LAYOUT_ROWS) whose voxels all have w > 0 and tap rows within a
+ * bound the host derives from the plane's pitch (so that a 32-bit byte
+ * offset cannot wrap) leaves such rows unclamped: their offsets fall
+ * outside the plane's buffer range and the loads return zero without
+ * touching memory; other launches, and FP32 storage (faster clamped),
+ * clamp.  -1 reads the setting back.  Returns the setting or
+ * FDK_ERR_INVALID_ARG.  The environment variable FDK_ROWS_FREE=0 sets the
+ * initial value to 1.
  */
 int fdk_set_row_clamp(int mode);
 
