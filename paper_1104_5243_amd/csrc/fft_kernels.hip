@@ -630,8 +630,14 @@ __device__ __forceinline__ void forward4096(double2 (&v)[4][4], double* x, const
     for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
+            // branch-free, so that the loads are in flight together:
+            // load(p, in) reads element p < W, in telling whether it is
+            // the real one (the ramp's tap gradient at 128^3: 0.66 against
+            // 0.58 ms with a test per element)
             const int p = pos1(t, q, b);
-            v[q][b] = p < W ? load(p) : double2{0.0, 0.0};
+            const bool in = p < W;
+            const double2 val = load(min(p, W - 1), in);
+            v[q][b] = in ? val : double2{0.0, 0.0};
         }
     r16_fwd<true, false>(v, t, c, tw);
     __syncthreads();
@@ -810,12 +816,16 @@ __global__ __launch_bounds__(kF16Threads, 2) void fft_xcorr4096_partial_kernel(F
         const float* x0 = a.in + (size_t)r0 * a.W;
         const float* d0 = a.dout + (size_t)r0 * a.W;
         double2 zx[4][4], zd[4][4];
-        forward4096(zx, x, c, tw, t, a.W, [&](int p) {
-            return double2{(double)x0[p], two ? (double)x0[a.W + p] : 0.0};
+        const float* x1 = two ? x0 + a.W : x0;  // a row that exists
+        const float* d1 = two ? d0 + a.W : d0;
+        forward4096(zx, x, c, tw, t, a.W, [&](int p, bool) {
+            const double u0 = (double)x0[p], u1 = (double)x1[p];
+            return double2{u0, two ? u1 : 0.0};
         });
-        forward4096(zd, x, c, tw, t, a.W, [&](int p) {
-            const double2 d = {(double)d0[p], two ? (double)d0[a.W + p] : 0.0};
-            accb += d.x + d.y;
+        forward4096(zd, x, c, tw, t, a.W, [&](int p, bool in) {
+            const double u0 = (double)d0[p], u1 = (double)d1[p];
+            const double2 d = {u0, two ? u1 : 0.0};
+            accb += in ? d.x + d.y : 0.0;
             return d;
         });
 #pragma unroll
