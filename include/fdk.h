@@ -99,6 +99,29 @@ int fdk_backproject_ex(float* volume, int N, float voxel_size, const float origi
                        const double* P_mats, const float* view_scale, int flags, void* stream);
 
 /*
+ * fdk_backproject_noalloc - fdk_backproject_ex's fused path for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid allocation).  It calls no hipMalloc, hipFree or allocating
+ * library routine and records no events: each pass's staged planes and
+ * folded matrices go to a fixed scratch array of FDK_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every device it runs on until the process ends,
+ * and the matrices reach it through a kernel's arguments.
+ *   Arguments as fdk_backproject_ex (flags fixed to FDK_KERNEL_FUSED).
+ *   Views per pass: at most the fdk_set_batch value, at most 64, and as many
+ *   staged views as fit the scratch array (27 FP32 or 54 FP16/BF16 views of
+ *   1248x960 in the default layout); results equal fdk_backproject_ex's run
+ *   with that batch.  A single staged view larger than the array is rejected
+ *   with FDK_ERR_UNSUPPORTED before anything is enqueued.
+ *   Every call on a device shares that device's scratch array and leaves its
+ *   contents behind: two calls that may overlap on one device (different
+ *   streams, or host threads) race and must be ordered by the caller.
+ */
+#define FDK_NOALLOC_SCRATCH_BYTES ((size_t)256 * 1024 * 1024)
+int fdk_backproject_noalloc(float* volume, int N, float voxel_size, const float origin[3],
+                            const void* proj_stack, int proj_dtype, int n_views, int H, int W,
+                            const double* P_mats, const float* view_scale, void* stream);
+
+/*
  * fdk_backproject_plain - the plain FP32 path: one thread per voxel, the
  * listing's arithmetic (world coordinates, one IEEE division per
  * coordinate, bounds-checked taps), all views of a batch accumulated in a

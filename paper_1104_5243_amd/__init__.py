@@ -28,7 +28,8 @@ KERNEL_FUSED, KERNEL_PLAIN = 0, 1
 
 # every symbol include/fdk.h declares
 EXPORTS = (
-    "fdk_backproject", "fdk_backproject_ex", "fdk_backproject_plain", "fdk_forward_project",
+    "fdk_backproject", "fdk_backproject_ex", "fdk_backproject_noalloc", "fdk_backproject_plain",
+    "fdk_forward_project",
     "fdk_prefilter", "fdk_conv_rows", "fdk_conv_rows_wgrad_workspace", "fdk_conv_rows_wgrad",
     "fdk_scale_groups", "fdk_group_dot", "fdk_relu_backward", "fdk_matvec", "fdk_adam", "fdk_mse",
     "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
@@ -62,6 +63,7 @@ def lib():
                             ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_float)
         L.fdk_backproject.argtypes = [vp, i, f, fp, vp, i, i, i, dp, vp]
         L.fdk_backproject_ex.argtypes = [vp, i, f, fp, vp, i, i, i, i, dp, fp, i, vp]
+        L.fdk_backproject_noalloc.argtypes = [vp, i, f, fp, vp, i, i, i, i, dp, fp, vp]
         L.fdk_backproject_plain.argtypes = [vp, i, f, fp, vp, i, i, i, dp, vp]
         L.fdk_forward_project.argtypes = [vp, i, i, i, dp, vp, i, f, fp, vp]
         L.fdk_update_probe.argtypes = [vp, ctypes.c_size_t, f, vp]
@@ -180,6 +182,34 @@ def backproject(volume, proj, P, voxel_size: float, origin, stream=None, kernel:
         rc = lib().fdk_backproject_ex(
             ctypes.c_void_p(volume.data_ptr()), N, float(voxel_size), op,
             ctypes.c_void_p(proj.data_ptr()), dtype, V, H, W, Pp, vs_ptr, flags,
+            _stream_ptr(stream, volume.device))
+    _check(rc)
+    return volume
+
+
+def backproject_noalloc(volume, proj, P, voxel_size: float, origin, stream=None,
+                        view_scale=None):
+    """As `backproject` (fused kernel), through the entry point that
+    allocates nothing: the staged views go to the library's fixed scratch
+    array (see fdk_backproject_noalloc in include/fdk.h)."""
+    import torch
+    N = _volume(volume)
+    _dev_tensor(proj, "proj", (torch.float32, torch.float16, torch.bfloat16), 3)
+    if proj.device != volume.device:
+        raise ValueError("volume and proj must be on the same device")
+    V, H, W = proj.shape
+    Pm, Pp = _mats(P, V)
+    o, op = _origin(origin)
+    dtype = {torch.float32: DTYPE_F32, torch.float16: DTYPE_F16, torch.bfloat16: DTYPE_BF16}[
+        proj.dtype]
+    vs_arr, vs_ptr = None, None
+    if view_scale is not None:
+        vs_arr = np.ascontiguousarray(np.asarray(view_scale, dtype=np.float32).reshape(V))
+        vs_ptr = vs_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    with torch.cuda.device(volume.device):
+        rc = lib().fdk_backproject_noalloc(
+            ctypes.c_void_p(volume.data_ptr()), N, float(voxel_size), op,
+            ctypes.c_void_p(proj.data_ptr()), dtype, V, H, W, Pp, vs_ptr,
             _stream_ptr(stream, volume.device))
     _check(rc)
     return volume

@@ -388,18 +388,49 @@ size_t planes_region(size_t n, size_t plane_bytes)
     return (n * plane_bytes + 255) & ~size_t(255);
 }
 
+// Staged-plane geometry of a fused backprojection call.
+struct FusedPlan {
+    int Hp, Wp, layout;
+    size_t esz, elem, plane_bytes;
+    double vlim;  // bound on |v'| for unclamped rows (0: always clamp)
+};
+
+int plan_fused(int dtype, int H, int W, FusedPlan* F)
+{
+    F->Hp = H + 2 * kPad;
+    F->Wp = ((W + 2 * kPad + 63) / 64) * 64;
+    F->esz = storage_size(dtype);
+    F->layout = g_layout;
+    F->elem = F->esz * layout_width(F->layout);
+    F->plane_bytes = (size_t)F->Hp * F->Wp * F->elem;
+    if (F->plane_bytes >= (size_t(1) << 31))
+        return fail(FDK_ERR_UNSUPPORTED, "staged view of %zu bytes exceeds 2 GiB",
+                    F->plane_bytes);
+    // Rows outside the staged plane may be left to the buffer's range check
+    // (no clamp of v) when a tap row R satisfies |R| * Wp * elem < 2^31, so
+    // that its byte offset lands outside [0, plane_bytes) without wrapping:
+    // bound |v'| by a quarter of that, less the centring.  Only 16-bit
+    // storage, with one load per tap pair (not the rows layout, whose second
+    // load adds an offset): on fdk512 the unclamped FP16 kernel took 30.9
+    // against 31.5 ms, while the FP32 one, whatever the load schedule, was
+    // 2-15 % slower than with the clamp.
+    F->vlim = (F->layout == kRows || dtype == FDK_DTYPE_F32)
+                  ? 0.0
+                  : 0.25 * 2147483648.0 / ((double)F->Wp * (double)F->elem) -
+                        (double)((H - 1) / 2 + kPad + 2);
+    return FDK_OK;
+}
+
 int run_fused(float* volume, int N, float voxel_size, const float* origin, const void* proj,
               int dtype, int n_views, int H, int W, const double* P, const float* view_scale,
               hipStream_t stream)
 {
-    const int Hp = H + 2 * kPad;
-    const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
-    const size_t esz = storage_size(dtype);
-    const int layout = g_layout;
-    const size_t elem = esz * layout_width(layout);
-    const size_t plane_bytes = (size_t)Hp * Wp * elem;
-    if (plane_bytes >= (size_t(1) << 31))
-        return fail(FDK_ERR_UNSUPPORTED, "staged view of %zu bytes exceeds 2 GiB", plane_bytes);
+    FusedPlan F;
+    int rc = plan_fused(dtype, H, W, &F);
+    if (rc != FDK_OK) return rc;
+    const int Hp = F.Hp, Wp = F.Wp, layout = F.layout;
+    const size_t esz = F.esz, plane_bytes = F.plane_bytes;
+    const double vlim = F.vlim;
     int batch = g_batch;
     if ((size_t)batch * plane_bytes > kMaxStagingBytes)
         batch = (int)std::max<size_t>(1, kMaxStagingBytes / plane_bytes);
@@ -411,22 +442,10 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     std::lock_guard<std::mutex> lock(g_stage_mu);
     Staging* st = nullptr;
     const size_t planes = planes_region(batch, plane_bytes);
-    int rc = acquire_staging(planes + 48 * (size_t)n_views, stream, &st);
+    rc = acquire_staging(planes + 48 * (size_t)n_views, stream, &st);
     if (rc != FDK_OK) return rc;
     A.img = st->ptr;
     float* mats = (float*)((char*)st->ptr + planes);
-    // Rows outside the staged plane may be left to the buffer's range check
-    // (no clamp of v) when a tap row R satisfies |R| * Wp * elem < 2^31, so
-    // that its byte offset lands outside [0, plane_bytes) without wrapping:
-    // bound |v'| by a quarter of that, less the centring.  Only 16-bit
-    // storage, with one load per tap pair (not the rows layout, whose second
-    // load adds an offset): on fdk512 the unclamped FP16 kernel took 30.9
-    // against 31.5 ms, while the FP32 one, whatever the load schedule, was
-    // 2-15 % slower than with the clamp.
-    const double vlim = (layout == kRows || dtype == FDK_DTYPE_F32)
-                            ? 0.0
-                            : 0.25 * 2147483648.0 / ((double)Wp * (double)elem) -
-                                  (double)((H - 1) / 2 + kPad + 2);
     Batches B;
     rc = fold_and_upload(st, mats, P, view_scale, n_views, batch, N, voxel_size, origin, H, W,
                          vlim, stream, &B);
@@ -457,6 +476,98 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     }
     hipError_t e = hipEventRecord(st->last_use, stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return FDK_OK;
+}
+
+// ---- allocation-free backprojection: one fixed scratch array per device ----
+// Holds a pass's staged planes followed by its folded matrices.  Every call
+// of fdk_backproject_noalloc on a device shares that device's copy.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[FDK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// The calling device's copy of `scratch`: its address is looked up once per
+// device (with that device current) and kept; host code uses that address,
+// never the array's name, which on the host is only a stand-in.
+int scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(FDK_ERR_UNSUPPORTED, "device %d beyond the %d the scratch table holds", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(FDK_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FDK_OK;
+}
+
+// The fused backprojection with the staged planes and matrices of each
+// pass in the device's scratch array: no allocation, no pinned copy (the
+// matrices travel in a kernel's arguments), no library events.
+int run_fused_noalloc(float* volume, int N, float voxel_size, const float* origin,
+                      const void* proj, int dtype, int n_views, int H, int W, const double* P,
+                      const float* view_scale, hipStream_t stream)
+{
+    FusedPlan F;
+    int rc = plan_fused(dtype, H, W, &F);
+    if (rc != FDK_OK) return rc;
+    const size_t bytes = FDK_NOALLOC_SCRATCH_BYTES;
+    // views per pass: as many planes as fit with their matrices, at most
+    // the configured batch and what one matrix upload carries
+    int batch = std::min(std::min((int)g_batch, kPutMatsMax), n_views);
+    while (batch > 0 && planes_region(batch, F.plane_bytes) + 48 * (size_t)batch > bytes) --batch;
+    if (batch < 1)
+        return fail(FDK_ERR_UNSUPPORTED,
+                    "a staged view of %zu bytes does not fit the %zu-byte scratch array",
+                    F.plane_bytes, bytes);
+    void* base = nullptr;
+    rc = scratch_address(&base);
+    if (rc != FDK_OK) return rc;
+
+    FusedArgs A = {};
+    setup_args(A, volume, N, H, W, F.Wp, (long long)F.Hp * F.Wp, fused_z(dtype));
+    A.img = base;
+    float* mats = (float*)((char*)base + planes_region(batch, F.plane_bytes));
+    PutMatsArgs M;
+    M.dst = mats;
+    for (int v0 = 0; v0 < n_views; v0 += batch) {
+        const int cnt = std::min(batch, n_views - v0);
+        bool rows_free = false;
+        const bool wcheck = fold_batch(A, M.m, P, view_scale, v0, cnt, N, voxel_size, origin,
+                                       H, W, F.vlim, &rows_free);
+        M.count = cnt;
+        hipError_t e = launch_put_mats(M, stream);
+        if (e != hipSuccess) return hip_fail(e, "matrix upload launch");
+        StageArgs S;
+        S.src = (const char*)proj + (size_t)v0 * H * W * F.esz;
+        S.dst = base;
+        S.H = H;
+        S.W = W;
+        S.Hp = F.Hp;
+        S.Wp = F.Wp;
+        S.count = cnt;
+        S.layout = F.layout;
+        e = launch_stage(S, dtype, stream);
+        if (e != hipSuccess) return hip_fail(e, "stage launch");
+        A.count = cnt;
+        A.m = mats;
+        e = launch_fused(A, dtype, F.layout, wcheck, g_rows_free && rows_free && !wcheck, stream);
+        if (e != hipSuccess) return hip_fail(e, "backprojection launch");
+    }
     return FDK_OK;
 }
 
@@ -634,6 +745,23 @@ int fdk_backproject(float* volume, int N, float voxel_size, const float origin[3
 {
     return fdk_backproject_ex(volume, N, voxel_size, origin, proj_stack, FDK_DTYPE_F32, n_views,
                               H, W, P_mats, nullptr, FDK_KERNEL_FUSED, stream);
+}
+
+int fdk_backproject_noalloc(float* volume, int N, float voxel_size, const float origin[3],
+                            const void* proj_stack, int proj_dtype, int n_views, int H, int W,
+                            const double* P_mats, const float* view_scale, void* stream)
+{
+    g_err.clear();
+    int rc = validate_common(volume, N, voxel_size, origin, proj_stack, n_views, H, W, P_mats);
+    if (rc != FDK_OK || n_views == 0) return rc;
+    if (proj_dtype != FDK_DTYPE_F32 && proj_dtype != FDK_DTYPE_F16 && proj_dtype != FDK_DTYPE_BF16)
+        return fail(FDK_ERR_INVALID_ARG, "unknown proj_dtype %d", proj_dtype);
+    if (view_scale)
+        for (int i = 0; i < n_views; ++i)
+            if (!(std::isfinite(view_scale[i]) && view_scale[i] > 0.0f))
+                return fail(FDK_ERR_INVALID_ARG, "view_scale[%d] must be finite and > 0", i);
+    return run_fused_noalloc(volume, N, voxel_size, origin, proj_stack, proj_dtype, n_views, H,
+                             W, P_mats, view_scale, (hipStream_t)stream);
 }
 
 int fdk_backproject_plain(float* volume, int N, float voxel_size, const float origin[3],

@@ -548,6 +548,20 @@ hipError_t launch_plain(const PlainArgs& a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
+// matrices from the kernel arguments to device memory
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void put_mats_kernel(const PutMatsArgs a)
+{
+    for (int i = threadIdx.x; i < 12 * a.count; i += 256) a.dst[i] = a.m[i];
+}
+
+hipError_t launch_put_mats(const PutMatsArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(put_mats_kernel, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // update probe
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void update_probe_kernel(float* a, size_t n, float s)

@@ -82,6 +82,16 @@ struct PlainArgs {
     float m[kPlainBatch][12];
 };
 
+// A batch's folded matrices carried in the kernel arguments, written to
+// device memory by a one-block kernel (used where the library may not copy
+// them from pinned host memory).
+constexpr int kPutMatsMax = 64;
+struct PutMatsArgs {
+    float* dst;          // count x 12 floats
+    int count;           // <= kPutMatsMax
+    float m[kPutMatsMax * 12];
+};
+
 struct StageArgs {
     const void* src;     // first view of the batch, H*W elements per view
     void* dst;           // count planes of Hp*Wp elements
@@ -107,6 +117,7 @@ hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck
                         hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, hipStream_t s);
 hipError_t launch_update_probe(float* a, size_t n, float s, hipStream_t st);
+hipError_t launch_put_mats(const PutMatsArgs& a, hipStream_t s);
 hipError_t launch_zero(float* a, size_t n, hipStream_t st);
 // forward projection of a.vol into the padded planes at a.img (scatter)
 hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s);

@@ -184,3 +184,32 @@ def test_header_is_c_and_library_links_from_c(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, (out.returncode, out.stdout, out.stderr)
     assert out.stdout.strip() == "ok"
+
+
+def test_noalloc_rejects_a_view_larger_than_its_scratch():
+    """A single staged view beyond the fixed scratch array is refused before
+    any HIP call (8192 x 8192 FP32 in the default layout: ~541 MB)."""
+    P = np.tile(np.eye(3, 4), (2, 1, 1)).astype(np.float64)
+    o = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    rc = fdk.lib().fdk_backproject_noalloc(FAKE, 8, 1.0, o, FAKE, 0, 2, 8192, 8192,
+                                           P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           None, None)
+    assert rc == fdk.FDK_ERR_UNSUPPORTED
+    assert "scratch" in fdk.last_error()
+
+
+@pytest.mark.parametrize("over,needle", [(dict(volume=None), "volume"), (dict(dtype=5), "proj_dtype"),
+                                         (dict(scale=-1.0), "view_scale")])
+def test_noalloc_validates_before_launch(over, needle):
+    P = np.tile(np.eye(3, 4), (2, 1, 1)).astype(np.float64)
+    o = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    a = dict(volume=FAKE, dtype=0, scale=None)
+    a.update(over)
+    sc = None
+    if a["scale"] is not None:
+        sc = (ctypes.c_float * 2)(a["scale"], 1.0)
+    rc = fdk.lib().fdk_backproject_noalloc(a["volume"], 8, 1.0, o, FAKE, a["dtype"], 2, 4, 4,
+                                           P.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           sc, None)
+    assert rc == fdk.FDK_ERR_INVALID_ARG
+    assert needle in fdk.last_error()
