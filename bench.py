@@ -160,6 +160,85 @@ def bench_forward(args, torch, fdk, synth, dev):
     return out
 
 
+def bench_autograd(args, torch, fdk, synth, dev):
+    """The differentiable pair at its stated size: a batch of 8 volumes of
+    256^3, 248 views of 624x480.  One step = BackProject forward (8
+    backprojections) and, through autograd, its backward (8 forward
+    projections of the volume gradient)."""
+    import numpy as np
+
+    import oracle
+    from paper_1104_5243_amd import autograd as ag
+    geom, ell, vs, origin, N = synth.workload("fdk256x8")
+    V, H, W = geom.n_views, geom.H, geom.W
+    B = 8
+    t0 = time.time()
+    stacks = []
+    for k in range(B):
+        e = synth.ellipsoid_phantom(5243 + k)
+        stacks.append(torch.from_numpy(synth.filtered_projections(geom, e)))
+    p = torch.stack(stacks).to(dev).requires_grad_(True)
+    del stacks
+    log(f"autograd: {B} stacks of {V} views {W}x{H} in {time.time() - t0:.1f}s")
+    g = torch.Generator(device=dev).manual_seed(4)
+    wv = torch.rand(B, N, N, N, device=dev, generator=g)
+
+    def step():
+        p.grad = None
+        vol = ag.backproject_op(p, geom.P, N, vs, origin)
+        vol.backward(wv)
+
+    t, kms, launches = _timed(torch, fdk, step, args.warmup, args.steps)
+    pairs = 2.0 * B * float(N) ** 3 * V  # both passes visit every (voxel, view) pair
+    ks = kms / 1e3
+    ach = FLOP_PER_UPDATE * pairs * args.steps / ks / 1e12
+    log(f"autograd: {t * 1e3:.2f} ms/step, {pairs / t / 1e9:.1f} GUP/s; {launches} launches, "
+        f"{kms / args.steps:.2f} ms of library kernels per step")
+    tc, err_f, err_g = None, None, None
+    if not args.no_extras:
+        # item 0 against the oracle: two 32^3 blocks of the forward result,
+        # and 3 views of the gradient (the forward projection of wv[0])
+        vol = ag.backproject_op(p.detach(), geom.P, N, vs, origin)
+        step()
+        torch.cuda.synchronize()
+        pr = p.detach()[0].cpu().numpy()
+        num = den = 0.0
+        t0 = time.perf_counter()
+        for box in (((112, 32), (112, 32), (112, 32)), ((16, 32), (200, 32), (40, 32))):
+            (x0, nx), (y0, ny), (z0, nz) = box
+            ref = oracle.backproject(pr, geom.P, N, vs, origin, box=box)
+            got = vol[0, z0:z0 + nz, y0:y0 + ny, x0:x0 + nx].double().cpu().numpy()
+            num += float(((got - ref) ** 2).sum())
+            den += float((ref ** 2).sum())
+        tc = time.perf_counter() - t0
+        err_f = (num / den) ** 0.5
+        views = [0, 123, 247]
+        refg = oracle.forward_project(wv[0].double().cpu().numpy(), geom.P[views], H, W, vs,
+                                      origin)
+        err_g = oracle.rel_rmse(p.grad[0, views].double().cpu().numpy(), refg)
+        log(f"autograd item 0 vs oracle: forward blocks {err_f:.3e}, gradient views {err_g:.3e}")
+    out = _common(
+        args, "differentiable pair voxel-view pairs/s, batch 8 x 256^3, 248 views of 624x480",
+        round(pairs / t / 1e9, 2), "GUP/s", t, "f32",
+        f"fdk256x8 autograd: BackProject forward + ForwardProject backward of {B} x {N}^3 "
+        f"FP32 volumes, {V} views of {W}x{H}",
+        {"bound": "alu", "achieved": round(ach, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
+         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+         "kernel": "bp_fused_kernel<f32> + fp_lds_kernel (31 flop per pair and pass)",
+         "launches_per_step": launches // args.steps,
+         "kernel_ms_per_step": round(kms / args.steps, 3)},
+        None if tc is None else
+        {"value": round(2 * 32 ** 3 * V / tc / 1e9, 4), "unit": "GUP/s",
+         "cores": oracle.threads(), "kind": "oracle",
+         "sample": f"two 32^3 blocks of item 0's backprojection x all {V} views, FP64, "
+                   f"{tc:.2f} s"})
+    out["config"]["batch"] = B
+    if err_f is not None:
+        out["rel_rmse_vs_oracle"] = {"forward_blocks": float(f"{err_f:.3e}"),
+                                     "gradient_views": float(f"{err_g:.3e}")}
+    return out
+
+
 def bench_prefilter(args, torch, fdk, synth, dev):
     """Feldkamp pre-filter (cosine x Parker x Ram-Lak, FP64 inside) of the
     496 line-integral views of 1248x960."""
@@ -308,11 +387,12 @@ def main() -> int:
                     help="z slices of the 512^3 volume in the CPU-baseline sample")
     ap.add_argument("--probe-hbm", action="store_true",
                     help="also run the update benchmark a[i] = s*a[i] over 2 GiB")
-    ap.add_argument("--path", choices=("backproject", "forward", "prefilter", "learn-step"),
+    ap.add_argument("--path", choices=("backproject", "forward", "prefilter", "learn-step",
+                                        "autograd"),
                     default="backproject",
                     help="which part to measure: the backprojection (default), the matched "
-                         "forward projector, the Feldkamp pre-filter, or one training step "
-                         "of the learned filter")
+                         "forward projector, the Feldkamp pre-filter, one training step "
+                         "of the learned filter, or the differentiable pair (batch of 8)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -335,7 +415,8 @@ def main() -> int:
     torch.cuda.set_device(dev)
     if args.path != "backproject":
         out = {"forward": bench_forward, "prefilter": bench_prefilter,
-               "learn-step": bench_learn_step}[args.path](args, torch, fdk, synth, dev)
+               "learn-step": bench_learn_step, "autograd": bench_autograd}[args.path](
+            args, torch, fdk, synth, dev)
         print(json.dumps(out), flush=True)
         return 0
 

@@ -14,8 +14,9 @@
  *              [(i*H + k)*W + j]; the pixel's centre is at u = j, v = k.
  *   P_mats     host double, n_views*12, row-major 3x4 per view mapping
  *              homogeneous world mm (x, y, z, 1) to (u w, v w, w).
- *              Read during the call only (folded and rounded to FP32 on the
- *              host; the library keeps no pointer to it).
+ *              Read during the call only (folded into the volume's centred
+ *              index frame in FP64 on the host and copied to the device; the
+ *              library keeps no pointer to it).
  *   origin     host float[3].
  *   stream     a hipStream_t passed as void*; NULL is the null stream.
  * Semantics:
@@ -99,6 +100,27 @@ int fdk_backproject_ex(float* volume, int N, float voxel_size, const float origi
                        const double* P_mats, const float* view_scale, int flags, void* stream);
 
 /*
+ * fdk_convert_storage - an FP32 stack in reduced-precision storage for
+ * fdk_backproject_ex (FP16 or BF16 taps halve the gather bytes; the
+ * arithmetic stays FP32).
+ *   dst         device, n_views*H*W 16-bit elements (IEEE binary16 or bfloat16
+ *               bit patterns), overwritten
+ *   src         device float[n_views*H*W]
+ *   dtype       FDK_DTYPE_F16: view i is multiplied by 4^k_i, k_i the largest
+ *               integer with 4^k_i max|view i| <= 2^14 (clipped to [-60, 60];
+ *               0 for an all-zero view), then rounded to nearest even;
+ *               view_scale[i] = 4^-k_i is written (device float[n_views],
+ *               required) and undoes the scaling exactly when passed to
+ *               fdk_backproject_ex.  (Filtered projections are ~1e-4, where
+ *               FP16 would be subnormal.)
+ *               FDK_DTYPE_BF16: each value rounded to nearest even (FP32's
+ *               range); view_scale is not used and may be NULL.
+ * Asynchronous on `stream`; the caller copies view_scale to the host.
+ */
+int fdk_convert_storage(void* dst, const float* src, int n_views, int H, int W, int dtype,
+                        float* view_scale, void* stream);
+
+/*
  * fdk_backproject_noalloc - fdk_backproject_ex's fused path for callers that
  * cannot allocate device memory (code under HIP graph capture, serving loops
  * that forbid allocation).  It calls no hipMalloc, hipFree or allocating
@@ -134,11 +156,15 @@ int fdk_backproject_plain(float* volume, int N, float voxel_size, const float or
 
 /*
  * fdk_forward_project - the matched cone-beam forward projector, the exact
- * transpose of fdk_backproject: every voxel's value times 1/w^2 is spread
- * onto the four pixels the backprojection reads, with the same bilinear
- * weights; pixels outside the detector are dropped.  ACCUMULATES into
- * proj_stack (+=).  Uses floating-point atomics, so results may differ
- * between runs in the last bits.
+ * transpose of fdk_backproject (FP32 storage, FDK_DIVIDE_RCP): every
+ * voxel's value times 1/w^2 is spread onto the four pixels the
+ * backprojection reads, with the same bilinear weights, computed by the same
+ * operations; pixels outside the detector are dropped.  ACCUMULATES into
+ * proj_stack (+=).  Each view's sums are formed in 64-bit fixed point
+ * (integer atomics, whose order does not change the result), so the output
+ * is the same on every run; the one exception is a batch of views in which
+ * some voxel lies on or behind a source plane (w <= 0), whose sums are
+ * formed with float atomics and may differ between runs in the last bits.
  *   proj_stack  device float[n_views*H*W], accumulated
  *   volume      device float[N^3]
  *   other arguments as fdk_backproject.
@@ -279,6 +305,29 @@ int fdk_set_batch(int views_per_pass);
 #define FDK_LAYOUT_DPAIRS 3
 #define FDK_LAYOUT_DQUADS 4
 int fdk_set_layout(int layout);
+
+/*
+ * Reciprocal of the fused backprojection's part 1 (the divide variants of
+ * the paper's accuracy study, Section 7.2).  Per voxel and view, u and v
+ * are the anchored numerators divided by w, and the weight is 1/w^2:
+ *   FDK_DIVIDE_RCP     r = v_rcp_f32(w) (about 1 ulp), u = num_u r, v = num_v r,
+ *                      weight r^2 (the default)
+ *   FDK_DIVIDE_RCP_NR  as RCP, r refined by one Newton-Raphson step
+ *                      r += r (1 - w r)
+ *   FDK_DIVIDE_IEEE    u = num_u / w, v = num_v / w, r = 1 / w, correctly
+ *                      rounded divisions (the paper's divps variant)
+ *   FDK_DIVIDE_RCP12   r truncated to 12 significant bits, a stand-in for the
+ *                      paper's approximate rcpps (relative error < 2^-11)
+ * Non-default variants are built for the default layout (FDK_LAYOUT_DPAIRS)
+ * only; a fused call in another layout then fails with FDK_ERR_UNSUPPORTED.
+ * Applies to calls made after it; -1 reads the setting back.  Returns the
+ * setting or FDK_ERR_INVALID_ARG.
+ */
+#define FDK_DIVIDE_RCP 0
+#define FDK_DIVIDE_RCP_NR 1
+#define FDK_DIVIDE_IEEE 2
+#define FDK_DIVIDE_RCP12 3
+int fdk_set_divide(int mode);
 
 /*
  * Row clamping of the fused backprojection's taps (a tuning knob; results

@@ -29,11 +29,12 @@ KERNEL_FUSED, KERNEL_PLAIN = 0, 1
 # every symbol include/fdk.h declares
 EXPORTS = (
     "fdk_backproject", "fdk_backproject_ex", "fdk_backproject_noalloc", "fdk_backproject_plain",
-    "fdk_forward_project",
+    "fdk_forward_project", "fdk_convert_storage",
     "fdk_prefilter", "fdk_conv_rows", "fdk_conv_rows_wgrad_workspace", "fdk_conv_rows_wgrad",
     "fdk_scale_groups", "fdk_group_dot", "fdk_relu_backward", "fdk_matvec", "fdk_adam", "fdk_mse",
     "fdk_update_probe", "fdk_profile_begin", "fdk_profile_end", "fdk_set_batch",
-    "fdk_set_layout", "fdk_set_row_clamp", "fdk_release", "fdk_last_error", "fdk_version",
+    "fdk_set_layout", "fdk_set_row_clamp", "fdk_set_divide", "fdk_release", "fdk_last_error",
+    "fdk_version",
 )
 
 _lib = None
@@ -67,6 +68,7 @@ def lib():
         L.fdk_backproject_plain.argtypes = [vp, i, f, fp, vp, i, i, i, dp, vp]
         L.fdk_forward_project.argtypes = [vp, i, i, i, dp, vp, i, f, fp, vp]
         L.fdk_update_probe.argtypes = [vp, ctypes.c_size_t, f, vp]
+        L.fdk_convert_storage.argtypes = [vp, vp, i, i, i, i, vp, vp]
         d = ctypes.c_double
         L.fdk_prefilter.argtypes = [vp, vp, i, i, i, d, d, d, d, d, d, vp]
         sz = ctypes.c_size_t
@@ -83,6 +85,7 @@ def lib():
         L.fdk_profile_end.argtypes = [dp, ctypes.POINTER(ctypes.c_int)]
         L.fdk_set_batch.argtypes = [i]
         L.fdk_set_row_clamp.argtypes = [i]
+        L.fdk_set_divide.argtypes = [i]
         L.fdk_release.argtypes = []
         L.fdk_last_error.argtypes = []
         L.fdk_last_error.restype = ctypes.c_char_p
@@ -369,28 +372,29 @@ def update_probe(a, s: float = 1.0000001, stream=None):
     return a
 
 
-def to_storage(proj, dtype):
+def to_storage(proj, dtype, stream=None):
     """Convert an FP32 (n_views, H, W) device stack to reduced-precision
-    storage for `backproject`.  Returns (stack, view_scale): for float16 each
+    storage for `backproject` with the library's conversion kernels
+    (fdk_convert_storage).  Returns (stack, view_scale): for float16 each
     view is multiplied by a power of 4 that brings its largest magnitude to
-    [2^12, 2^14) before rounding (filtered projections are ~1e-4, where FP16
-    is subnormal), and view_scale = 4^-k undoes it exactly inside the
-    library.  For bfloat16 (FP32's range) view_scale is None."""
+    (2^12, 2^14] before rounding, and view_scale (host float32) undoes it
+    exactly inside the library; for bfloat16 view_scale is None."""
     import torch
     if dtype == torch.float32:
         return proj, None
-    if dtype == torch.bfloat16:
-        return proj.to(torch.bfloat16), None
-    if dtype != torch.float16:
+    if dtype not in (torch.float16, torch.bfloat16):
         raise ValueError(f"unsupported storage dtype {dtype}")
-    amax = proj.abs().amax(dim=(1, 2)).double().cpu().numpy()
-    k = np.zeros(len(amax))
-    nz = amax > 0
-    k[nz] = np.floor(np.log(2.0 ** 14 / amax[nz]) / np.log(4.0))
-    k = np.clip(k, -60, 60)
-    up = torch.from_numpy(4.0 ** k).to(device=proj.device, dtype=torch.float32)
-    stack = (proj * up[:, None, None]).to(torch.float16)
-    return stack, (4.0 ** -k).astype(np.float32)
+    _dev_tensor(proj, "proj", (torch.float32,), 3)
+    V, H, W = proj.shape
+    out = torch.empty((V, H, W), dtype=dtype, device=proj.device)
+    scale = torch.empty(V, dtype=torch.float32, device=proj.device) if dtype == torch.float16 \
+        else None
+    with torch.cuda.device(proj.device):
+        _check(lib().fdk_convert_storage(
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(proj.data_ptr()), V, H, W,
+            DTYPE_F16 if dtype == torch.float16 else DTYPE_BF16, _p(scale),
+            _stream_ptr(stream, proj.device)))
+    return out, (None if scale is None else scale.cpu().numpy())
 
 
 def profile_begin():
@@ -427,6 +431,17 @@ def set_row_clamp(clamp=None) -> bool:
     None reads it back.  Results are bit-identical either way."""
     code = -1 if clamp is None else (1 if clamp else 0)
     return _check(lib().fdk_set_row_clamp(code)) == 1
+
+
+DIVIDES = {"rcp": 0, "rcp_nr": 1, "ieee": 2, "rcp12": 3}
+
+
+def set_divide(mode=None) -> str:
+    """Reciprocal variant of the fused backprojection's part 1 (a name of
+    DIVIDES, or None to read it back); returns the variant in effect."""
+    code = -1 if mode is None else DIVIDES[mode]
+    got = _check(lib().fdk_set_divide(code))
+    return next(k for k, v in DIVIDES.items() if v == got)
 
 
 def release():

@@ -147,6 +147,8 @@ std::atomic<int> g_rows_free = []() {
     return (e && !std::strcmp(e, "0")) ? 0 : 1;
 }();
 constexpr size_t kMaxStagingBytes = size_t(8) << 30;
+// reciprocal variant of the fused backprojection (fdk_set_divide)
+std::atomic<int> g_divide{FDK_DIVIDE_RCP};
 
 // ---- validation -----------------------------------------------------------
 int validate_common(const void* volume, int N, float voxel_size, const float* origin,
@@ -282,6 +284,10 @@ void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long l
     A.skip_hi_v = (float)(H - kv) + 0.5f;
     A.in_lo_u = (float)(-1 - ku) - 0.5f;
     A.in_lo_v = (float)(-1 - kv) - 0.5f;
+    A.lo_iu = -ku - kPad;
+    A.hi_iu = W - ku;
+    A.lo_iv = -kv - kPad;
+    A.hi_iv = H - kv;
     A.origin_off = (kv + kPad) * Wp + (ku + kPad);
     A.c = 0.5f * (float)(N - 1);
     A.tiles_x = (N + kTileX - 1) / kTileX;
@@ -291,12 +297,13 @@ void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long l
     A.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
 }
 
-// Fold the matrices of views [v0, v0+cnt) into out (cnt x 12 floats);
-// returns whether some voxel may have w <= 0, sets *rows_free to whether
-// every view passes rows_bounded(vlim) (vlim <= 0: never), and sets the
-// workgroup order from the batch's mean ray direction.
-bool fold_batch(FusedArgs& A, float* out, const double* P, const float* view_scale, int v0,
-                int cnt, int N, float voxel_size, const float* origin, int H, int W,
+// Fold the matrices of views [v0, v0+cnt) into out (cnt x 12 floats, in
+// the batch's ray frame) and outq (cnt x 12 doubles, unrounded, columns x,
+// y, z, 1); returns whether some voxel may have w <= 0, sets *rows_free to
+// whether every view passes rows_bounded(vlim) (vlim <= 0: never), and sets
+// the workgroup order from the batch's mean ray direction.
+bool fold_batch(FusedArgs& A, float* out, double* outq, const double* P, const float* view_scale,
+                int v0, int cnt, int N, float voxel_size, const float* origin, int H, int W,
                 double vlim, bool* rows_free)
 {
     const int ku = (W - 1) / 2, kv = (H - 1) / 2;
@@ -312,7 +319,10 @@ bool fold_batch(FusedArgs& A, float* out, const double* P, const float* view_sca
         fold_matrix(P + 12 * (size_t)(v0 + j), N, voxel_size, origin, ku, kv, lambda, Q);
         wcheck |= needs_wcheck(Q, c);
         if (*rows_free) *rows_free = rows_bounded(Q, c, vlim);
-        for (int k = 0; k < 12; ++k) out[12 * (size_t)j + k] = (float)Q[k];
+        for (int k = 0; k < 12; ++k) {
+            out[12 * (size_t)j + k] = (float)Q[k];
+            outq[12 * (size_t)j + k] = Q[k];
+        }
         double d[3];
         source_direction(Q, d);
         for (int k = 0; k < 3; ++k) ray[k] += std::fabs(d[k]);
@@ -335,12 +345,16 @@ struct Batches {
     std::vector<int> v0, count, wcheck, rows_free, y_fastest;
 };
 
+// Device (and pinned host) matrix region of a call: n_views x 12 floats,
+// then n_views x 12 doubles.
+constexpr size_t kMatBytesPerView = 12 * sizeof(float) + 12 * sizeof(double);
+
 int fold_and_upload(Staging* st, float* dev, const double* P, const float* view_scale,
                     int n_views, int batch, int N, float voxel_size, const float* origin, int H,
                     int W, double vlim, hipStream_t stream, Batches* B)
 {
     hipError_t e;
-    const size_t floats = 12 * (size_t)n_views;
+    const size_t floats = kMatBytesPerView / sizeof(float) * (size_t)n_views;
     if (!st->mats_copied) {
         e = hipEventCreateWithFlags(&st->mats_copied, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -367,8 +381,10 @@ int fold_and_upload(Staging* st, float* dev, const double* P, const float* view_
     for (int v0 = 0; v0 < n_views; v0 += batch) {
         const int cnt = std::min(batch, n_views - v0);
         bool rows_free = false;
-        const bool wcheck = fold_batch(A, st->host_mats + 12 * (size_t)v0, P, view_scale, v0,
-                                       cnt, N, voxel_size, origin, H, W, vlim, &rows_free);
+        double* hq = (double*)(st->host_mats + 12 * (size_t)n_views);
+        const bool wcheck = fold_batch(A, st->host_mats + 12 * (size_t)v0, hq + 12 * (size_t)v0, P,
+                                       view_scale, v0, cnt, N, voxel_size, origin, H, W, vlim,
+                                       &rows_free);
         B->v0.push_back(v0);
         B->count.push_back(cnt);
         B->wcheck.push_back(wcheck ? 1 : 0);
@@ -390,7 +406,7 @@ size_t planes_region(size_t n, size_t plane_bytes)
 
 // Staged-plane geometry of a fused backprojection call.
 struct FusedPlan {
-    int Hp, Wp, layout;
+    int Hp, Wp, layout, divide;
     size_t esz, elem, plane_bytes;
     double vlim;  // bound on |v'| for unclamped rows (0: always clamp)
 };
@@ -414,6 +430,11 @@ int plan_fused(int dtype, int H, int W, FusedPlan* F)
     // load adds an offset): on fdk512 the unclamped FP16 kernel took 30.9
     // against 31.5 ms, while the FP32 one, whatever the load schedule, was
     // 2-15 % slower than with the clamp.
+    F->divide = g_divide;
+    if (F->divide != FDK_DIVIDE_RCP && F->layout != kDPairs)
+        return fail(FDK_ERR_UNSUPPORTED,
+                    "divide variant %d is built for the dpairs layout only (layout %d)",
+                    F->divide, F->layout);
     F->vlim = (F->layout == kRows || dtype == FDK_DTYPE_F32)
                   ? 0.0
                   : 0.25 * 2147483648.0 / ((double)F->Wp * (double)F->elem) -
@@ -442,10 +463,11 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     std::lock_guard<std::mutex> lock(g_stage_mu);
     Staging* st = nullptr;
     const size_t planes = planes_region(batch, plane_bytes);
-    rc = acquire_staging(planes + 48 * (size_t)n_views, stream, &st);
+    rc = acquire_staging(planes + kMatBytesPerView * (size_t)n_views, stream, &st);
     if (rc != FDK_OK) return rc;
     A.img = st->ptr;
     float* mats = (float*)((char*)st->ptr + planes);
+    const double* matsq = (const double*)(mats + 12 * (size_t)n_views);
     Batches B;
     rc = fold_and_upload(st, mats, P, view_scale, n_views, batch, N, voxel_size, origin, H, W,
                          vlim, stream, &B);
@@ -466,11 +488,12 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
         if (e != hipSuccess) return hip_fail(e, "stage launch");
         A.count = cnt;
         A.m = mats + 12 * (size_t)v0;
+        A.mq = matsq + 12 * (size_t)v0;
         A.y_fastest = B.y_fastest[b];
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
         e = launch_fused(A, dtype, layout, B.wcheck[b] != 0, g_rows_free && B.rows_free[b] != 0,
-                         stream);
+                         F.divide, stream);
         if (e != hipSuccess) return hip_fail(e, "backprojection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
     }
@@ -483,6 +506,7 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
 // Holds a pass's staged planes followed by its folded matrices.  Every call
 // of fdk_backproject_noalloc on a device shares that device's copy.
 constexpr int kMaxDevices = 64;
+constexpr int kNoallocMaxBatch = 64;  // views per pass (host-side matrix arrays below)
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices];
 
@@ -528,8 +552,10 @@ int run_fused_noalloc(float* volume, int N, float voxel_size, const float* origi
     const size_t bytes = FDK_NOALLOC_SCRATCH_BYTES;
     // views per pass: as many planes as fit with their matrices, at most
     // the configured batch and what one matrix upload carries
-    int batch = std::min(std::min((int)g_batch, kPutMatsMax), n_views);
-    while (batch > 0 && planes_region(batch, F.plane_bytes) + 48 * (size_t)batch > bytes) --batch;
+    int batch = std::min(std::min((int)g_batch, kNoallocMaxBatch), n_views);
+    while (batch > 0 &&
+           planes_region(batch, F.plane_bytes) + kMatBytesPerView * (size_t)batch > bytes)
+        --batch;
     if (batch < 1)
         return fail(FDK_ERR_UNSUPPORTED,
                     "a staged view of %zu bytes does not fit the %zu-byte scratch array",
@@ -542,16 +568,25 @@ int run_fused_noalloc(float* volume, int N, float voxel_size, const float* origi
     setup_args(A, volume, N, H, W, F.Wp, (long long)F.Hp * F.Wp, fused_z(dtype));
     A.img = base;
     float* mats = (float*)((char*)base + planes_region(batch, F.plane_bytes));
+    double* matsq = (double*)(mats + 12 * (size_t)batch);
+    float hm[kNoallocMaxBatch * 12];
+    double hq[kNoallocMaxBatch * 12];
     PutMatsArgs M;
-    M.dst = mats;
     for (int v0 = 0; v0 < n_views; v0 += batch) {
         const int cnt = std::min(batch, n_views - v0);
         bool rows_free = false;
-        const bool wcheck = fold_batch(A, M.m, P, view_scale, v0, cnt, N, voxel_size, origin,
+        const bool wcheck = fold_batch(A, hm, hq, P, view_scale, v0, cnt, N, voxel_size, origin,
                                        H, W, F.vlim, &rows_free);
-        M.count = cnt;
-        hipError_t e = launch_put_mats(M, stream);
-        if (e != hipSuccess) return hip_fail(e, "matrix upload launch");
+        hipError_t e;
+        for (int k0 = 0; k0 < cnt; k0 += kPutMatsMax) {
+            M.count = std::min(kPutMatsMax, cnt - k0);
+            M.dst = mats + 12 * (size_t)k0;
+            M.dstq = matsq + 12 * (size_t)k0;
+            std::memcpy(M.m, hm + 12 * k0, sizeof(float) * 12 * M.count);
+            std::memcpy(M.q, hq + 12 * k0, sizeof(double) * 12 * M.count);
+            e = launch_put_mats(M, stream);
+            if (e != hipSuccess) return hip_fail(e, "matrix upload launch");
+        }
         StageArgs S;
         S.src = (const char*)proj + (size_t)v0 * H * W * F.esz;
         S.dst = base;
@@ -565,7 +600,9 @@ int run_fused_noalloc(float* volume, int N, float voxel_size, const float* origi
         if (e != hipSuccess) return hip_fail(e, "stage launch");
         A.count = cnt;
         A.m = mats;
-        e = launch_fused(A, dtype, F.layout, wcheck, g_rows_free && rows_free && !wcheck, stream);
+        A.mq = matsq;
+        e = launch_fused(A, dtype, F.layout, wcheck, g_rows_free && rows_free && !wcheck,
+                         F.divide, stream);
         if (e != hipSuccess) return hip_fail(e, "backprojection launch");
     }
     return FDK_OK;
@@ -613,12 +650,31 @@ int fp_tile_entries(const float* mats, int cnt, int N)
     return cap;
 }
 
+// The largest 1/w^2 over the centred box [-c, c]^3 (w is affine: its
+// minimum is at a corner) for the folded FP64 matrices of `cnt` views, with
+// a small margin; 0 if w may be <= 0 somewhere.
+float batch_rmax2(const double* Q, int cnt, int N)
+{
+    const double c = 0.5 * (N - 1);
+    double wmin = INFINITY;
+    for (int j = 0; j < cnt; ++j)
+        for (int corner = 0; corner < 8; ++corner) {
+            const double x = (corner & 1) ? c : -c, y = (corner & 2) ? c : -c,
+                         z = (corner & 4) ? c : -c;
+            const double* q = Q + 12 * (size_t)j;
+            wmin = std::fmin(wmin, q[8] * x + q[9] * y + q[10] * z + q[11]);
+        }
+    if (!(wmin > 0.0)) return 0.0f;
+    return (float)(1.0 / (wmin * wmin) * (1.0 + 1e-5));
+}
+
 int run_forward(float* proj, int n_views, int H, int W, const double* P, const float* volume,
                 int N, float voxel_size, const float* origin, hipStream_t stream)
 {
     const int Hp = H + 2 * kPad;
     const int Wp = ((W + 2 * kPad + 63) / 64) * 64;
-    const size_t plane_bytes = (size_t)Hp * Wp * 4;
+    // 64-bit fixed-point sums (float in batches that need the w check)
+    const size_t plane_bytes = (size_t)Hp * Wp * 8;
     if (plane_bytes >= (size_t(1) << 31))
         return fail(FDK_ERR_UNSUPPORTED, "padded view of %zu bytes exceeds 2 GiB", plane_bytes);
     int batch = g_batch;
@@ -631,24 +687,34 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
 
     std::lock_guard<std::mutex> lock(g_stage_mu);
     Staging* st = nullptr;
+    // planes, then 256 bytes for the volume's largest |x|, then the matrices
     const size_t planes = planes_region(batch, plane_bytes);
-    int rc = acquire_staging(planes + 48 * (size_t)n_views, stream, &st);
+    int rc = acquire_staging(planes + 256 + kMatBytesPerView * (size_t)n_views, stream, &st);
     if (rc != FDK_OK) return rc;
-    A.img = st->ptr;
-    float* mats = (float*)((char*)st->ptr + planes);
+    A.acc64 = (unsigned long long*)st->ptr;
+    unsigned* vmax = (unsigned*)((char*)st->ptr + planes);
+    float* mats = (float*)((char*)st->ptr + planes + 256);
+    const double* matsq = (const double*)(mats + 12 * (size_t)n_views);
     Batches B;
     rc = fold_and_upload(st, mats, P, nullptr, n_views, batch, N, voxel_size, origin, H, W, 0.0,
                          stream, &B);
     if (rc != FDK_OK) return rc;
+    const double* host_q = (const double*)(st->host_mats + 12 * (size_t)n_views);
+    hipError_t e = launch_zero((float*)vmax, 4, stream);
+    if (e == hipSuccess) e = launch_fp_vmax(volume, (size_t)N * N * N, vmax, stream);
+    if (e != hipSuccess) return hip_fail(e, "volume maximum launch");
+    A.fp_vmax = vmax;
 
     for (size_t b = 0; b < B.v0.size(); ++b) {
         const int v0 = B.v0[b], cnt = B.count[b];
-        hipError_t e = launch_zero((float*)st->ptr, (size_t)cnt * Hp * Wp, stream);
+        e = launch_zero((float*)st->ptr, (size_t)cnt * Hp * Wp * 2, stream);
         if (e != hipSuccess) return hip_fail(e, "zero launch");
         A.count = cnt;
         A.m = mats + 12 * (size_t)v0;
+        A.mq = matsq + 12 * (size_t)v0;
         A.y_fastest = B.y_fastest[b];
         const bool wcheck = B.wcheck[b] != 0;
+        A.fp_rmax2 = wcheck ? 0.0f : batch_rmax2(host_q + 12 * (size_t)v0, cnt, N);
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
         if (wcheck || !g_fp_lds) {
@@ -665,17 +731,21 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
         if (e != hipSuccess) return hip_fail(e, "forward projection launch");
         if ((rc = timed_end(stream, t0)) != FDK_OK) return rc;
         UnstageArgs U;
-        U.planes = (const float*)st->ptr;
+        U.planes = (const unsigned long long*)st->ptr;
         U.dst = proj + (size_t)v0 * H * W;
         U.H = H;
         U.W = W;
         U.Hp = Hp;
         U.Wp = Wp;
         U.count = cnt;
+        U.fixed = wcheck ? 0 : 1;
+        U.N = N;
+        U.vmax = vmax;
+        U.rmax2 = A.fp_rmax2;
         e = launch_unstage_add(U, stream);
         if (e != hipSuccess) return hip_fail(e, "unstage launch");
     }
-    hipError_t e = hipEventRecord(st->last_use, stream);
+    e = hipEventRecord(st->last_use, stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     return FDK_OK;
 }
@@ -784,6 +854,25 @@ int fdk_forward_project(float* proj_stack, int n_views, int H, int W, const doub
                        (hipStream_t)stream);
 }
 
+int fdk_convert_storage(void* dst, const float* src, int n_views, int H, int W, int dtype,
+                        float* view_scale, void* stream)
+{
+    g_err.clear();
+    if (n_views < 0) return fail(FDK_ERR_INVALID_ARG, "n_views=%d < 0", n_views);
+    if (H < 1 || H > 32768 || W < 1 || W > 32768)
+        return fail(FDK_ERR_INVALID_ARG, "detector %dx%d outside [1, 32768]^2", W, H);
+    if (dtype != FDK_DTYPE_F16 && dtype != FDK_DTYPE_BF16)
+        return fail(FDK_ERR_INVALID_ARG, "dtype %d is not FDK_DTYPE_F16 or FDK_DTYPE_BF16", dtype);
+    if (n_views == 0) return FDK_OK;
+    if (!dst || !src) return fail(FDK_ERR_INVALID_ARG, "dst or src is NULL");
+    if (dtype == FDK_DTYPE_F16 && !view_scale)
+        return fail(FDK_ERR_INVALID_ARG, "FP16 storage needs view_scale");
+    hipError_t e = launch_convert(dst, src, n_views, (size_t)H * W,
+                                  dtype == FDK_DTYPE_F16 ? kF16 : kBF16, view_scale,
+                                  (hipStream_t)stream);
+    return e == hipSuccess ? FDK_OK : hip_fail(e, "conversion launch");
+}
+
 int fdk_update_probe(float* a, size_t n, float s, void* stream)
 {
     g_err.clear();
@@ -845,6 +934,16 @@ int fdk_set_layout(int layout)
         return fail(FDK_ERR_INVALID_ARG, "layout=%d is not one of 0..4", layout);
     g_layout = layout;
     return g_layout;
+}
+
+int fdk_set_divide(int mode)
+{
+    g_err.clear();
+    if (mode == -1) return g_divide;
+    if (mode < FDK_DIVIDE_RCP || mode > FDK_DIVIDE_RCP12)
+        return fail(FDK_ERR_INVALID_ARG, "divide mode %d is not one of 0..3", mode);
+    g_divide = mode;
+    return mode;
 }
 
 int fdk_set_row_clamp(int mode)

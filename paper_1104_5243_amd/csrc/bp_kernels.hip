@@ -22,6 +22,7 @@
 //   coordinates (two IEEE divisions, bounds-tested taps), for comparison.
 // stage: copies a batch of views into zero-padded planes.
 // update probe: a[i] = s * a[i], the paper's bandwidth benchmark.
+#include "anchor.h"
 #include "fdk_internal.h"
 #include "gfx950_util.h"
 
@@ -152,6 +153,91 @@ hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
+// storage conversion (FP32 stack -> FP16 with per-view powers of 4, or BF16)
+// ---------------------------------------------------------------------------
+// One workgroup per view: the largest |value| of the view, then k, the
+// largest integer with 4^k amax <= 2^14, clipped to [-60, 60] (k = 0 for an
+// all-zero view), and view_scale = 4^-k.  k is found from the exponent and
+// significand of amax exactly (no logarithms): with amax = m 2^e, m in
+// [1, 2) and t = 14 - e, 4^k amax <= 2^14 holds iff 2k <= t when m = 1 and
+// 2k <= t - 1 otherwise.
+__global__ __launch_bounds__(1024) void view_scale_kernel(const float* src, size_t view_len,
+                                                          float* view_scale)
+{
+    __shared__ float part[16];
+    const float* v = src + (size_t)blockIdx.x * view_len;
+    float amax = 0.0f;
+    // 16-byte loads where the view starts 16-byte aligned, the rest one by one
+    const size_t lead = ((16 - ((uintptr_t)v & 15)) & 15) / 4;
+    const size_t head = lead < view_len ? lead : view_len;
+    const size_t n4 = (view_len - head) / 4;
+    const float4* v4 = (const float4*)(v + head);
+    for (size_t i = threadIdx.x; i < n4; i += 1024) {
+        const float4 q = v4[i];
+        amax = fmaxf(amax, fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w))));
+    }
+    for (size_t i = threadIdx.x; i < head; i += 1024) amax = fmaxf(amax, fabsf(v[i]));
+    for (size_t i = head + 4 * n4 + threadIdx.x; i < view_len; i += 1024)
+        amax = fmaxf(amax, fabsf(v[i]));
+    for (int d = 32; d >= 1; d >>= 1) amax = fmaxf(amax, __shfl_xor(amax, d));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) amax = fmaxf(amax, part[w]);
+        int k = 0;
+        if (amax > 0.0f) {
+            int e;
+            const float m = 2.0f * frexpf(amax, &e);  // amax = m 2^(e-1), m in [1, 2)
+            const int t = 14 - (e - 1) - (m > 1.0f ? 1 : 0);
+            k = t >= 0 ? t / 2 : -((1 - t) / 2);  // floor(t / 2)
+            k = min(max(k, -60), 60);
+        }
+        view_scale[blockIdx.x] = __builtin_ldexpf(1.0f, -2 * k);
+    }
+}
+
+// dst = round-to-nearest-even(src / view_scale[view]) in FP16, or
+// round-to-nearest-even(src) in BF16 (view_scale unused).  blockIdx.y is
+// the view.  The FP16 scaling is an exponent shift (ldexp by 2k with
+// view_scale = 4^-k): exact, sign of zero kept, subnormals rounded once.
+template <typename TT>
+__global__ __launch_bounds__(256) void convert_kernel(uint16_t* dst, const float* src,
+                                                      size_t view_len, const float* view_scale)
+{
+    const size_t off = (size_t)blockIdx.y * view_len;
+    int shift = 0;
+    if constexpr (TT::id == kF16) {
+        int e;
+        frexpf(view_scale[blockIdx.y], &e);  // view_scale = 2^(e-1) = 4^-k
+        shift = 1 - e;                       // 2k
+    }
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < view_len; i += stride) {
+        float x = src[off + i];
+        if constexpr (TT::id == kF16) x = __builtin_ldexpf(x, shift);
+        dst[off + i] = from_f(TT{}, x);
+    }
+}
+
+hipError_t launch_convert(void* dst, const float* src, int n_views, size_t view_len, int storage,
+                          float* view_scale, hipStream_t s)
+{
+    if (storage == kF16)
+        hipLaunchKernelGGL(view_scale_kernel, dim3(n_views), dim3(1024), 0, s, src, view_len,
+                           view_scale);
+    size_t bx = (view_len + 255) / 256;
+    if (bx > 64) bx = 64;
+    const dim3 grid((unsigned)bx, (unsigned)n_views);
+    if (storage == kF16)
+        hipLaunchKernelGGL(convert_kernel<TF16>, grid, dim3(256), 0, s, (uint16_t*)dst, src,
+                           view_len, (const float*)view_scale);
+    else
+        hipLaunchKernelGGL(convert_kernel<TBF16>, grid, dim3(256), 0, s, (uint16_t*)dst, src,
+                           view_len, (const float*)view_scale);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // fused
 // ---------------------------------------------------------------------------
 // The four taps (tl, tr, bl, br) of element (iv, iu): `off` is the byte
@@ -268,24 +354,20 @@ __device__ __forceinline__ float bilerp16(TBF16, uint2 q, float au, float av)
 constexpr int kGroup = FDK_GROUP;
 static_assert(kWaveX * kWaveY == 64, "a wave covers 64 columns");
 
-// One view's contribution to the fused_z voxels of this thread.  CLAMP
-// selects the clamped tap addressing (needed when some voxel of the wave
-// may project outside the zero border of the staged plane); with VCLAMP
-// false only u is clamped, and a tap row outside the plane gives a byte
-// offset outside the buffer's range, which reads as zero (the host has
-// bounded the rows so that the offset cannot wrap into the plane).
-//
-// The matrices are in the batch's ray frame (column 0 transverse, column 1
-// along the rays).  The column base (u'w, v'w, w at z = 0) adds the
-// transverse term first and the ray term second (pt, pr: the thread's
-// coordinates on those axes), then each voxel its z term: the forward
-// projector, which walks the ray axis, rounds every pair's coordinates in
-// this same order.
-template <typename TT, int LAYOUT, bool WCHECK, bool CLAMP, bool VCLAMP>
-__device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_float* m, float pt,
-                                                float pr, float zp0,
-                                                __amdgpu_buffer_rsrc_t rsrc,
-                                                float (&acc)[fused_z(TT::id)])
+// One view's contribution to the fused_z voxels of this thread, from the
+// view's anchor (uniform over the wave) and the thread's offsets (d_t, d_r)
+// from the box's centre column; voxel i is slice i of the box.  Taps are
+// clamped into the staged plane's zero border (integer clamps of the
+// anchored indices); with VCLAMP false only u is clamped, and a tap row
+// outside the plane gives a byte offset outside the buffer's range, which
+// reads as zero (the host has bounded the rows so that the offset cannot
+// wrap into the plane).
+template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV>
+__device__ __forceinline__ void accumulate_view(
+    const FusedArgs& A, float uc, float vc, float wc, float su_t, float su_r, float su2,
+    float sv_t, float sv_r, float sv2, float sw_t, float sw_r, float sw2, int lo_u, int hi_u,
+    int lo_v, int hi_v, int base, float d_t, float d_r, __amdgpu_buffer_rsrc_t rsrc,
+    float (&acc)[fused_z(TT::id)])
 {
     constexpr int kFusedZ = fused_z(TT::id);
     using E = typename TT::elem;
@@ -293,10 +375,8 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_
     constexpr uint32_t kElem = sizeof(E) * layout_width(LAYOUT);
     const int Wp = A.Wp;
     const uint32_t row_bytes = (uint32_t)Wp * kElem;
-    const uint32_t centre_bytes = (uint32_t)A.origin_off * kElem;
-    const float bu = fmaf(m[1], pr, fmaf(m[0], pt, m[3]));
-    const float bv = fmaf(m[5], pr, fmaf(m[4], pt, m[7]));
-    const float bw = fmaf(m[9], pr, fmaf(m[8], pt, m[11]));
+    float bu, bv, bw;
+    column_base(uc, vc, wc, su_t, su_r, sv_t, sv_r, sw_t, sw_r, d_t, d_r, bu, bv, bw);
 #pragma unroll
     for (int g = 0; g < kFusedZ; g += kGroup) {
         float au[kGroup], av[kGroup], r2[kGroup];
@@ -304,23 +384,16 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_
         uint2 raw[kGroup];                                      // 16-bit storage
 #pragma unroll
         for (int q = 0; q < kGroup; ++q) {
-            const float zp = zp0 + (float)(g + q);
             // part 1
-            const float uw = fmaf(zp, m[2], bu);
-            const float vw = fmaf(zp, m[6], bv);
-            const float w = fmaf(zp, m[10], bw);
-            float r = __builtin_amdgcn_rcpf(w);
-            if (WCHECK) r = (w > 0.0f) ? r : 0.0f;
-            const float u = uw * r;
-            const float v = vw * r;
+            float u, v, r;
+            voxel_coords<DIV, WCHECK>(bu, bv, bw, su2, sv2, sw2, (float)(g + q), u, v, r);
             r2[q] = r * r;
             // part 2
             au[q] = __builtin_amdgcn_fractf(u);
             av[q] = __builtin_amdgcn_fractf(v);
-            const int iu = cvt_floor(CLAMP ? __builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u) : u);
-            const int iv =
-                cvt_floor(CLAMP && VCLAMP ? __builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v) : v);
-            const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * kElem + centre_bytes;
+            const int ju = med3_i32(cvt_floor(u), lo_u, hi_u);
+            const int jv = VCLAMP ? med3_i32(cvt_floor(v), lo_v, hi_v) : cvt_floor(v);
+            const uint32_t off = (uint32_t)(mad_i24_ub(jv, Wp, ju) + base) * kElem;
             if constexpr (kIsF32)
                 load_taps<LAYOUT>(TT{}, rsrc, off, row_bytes, tl[q], tr[q], bl[q], br[q]);
             else
@@ -354,7 +427,7 @@ __device__ __forceinline__ void accumulate_view(const FusedArgs& A, const const_
 #ifndef FDK_MIN_WAVES
 #define FDK_MIN_WAVES 8
 #endif
-template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP>
+template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV>
 __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused_kernel(const FusedArgs A)
 {
     using E = typename TT::elem;
@@ -380,54 +453,78 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     const int tx = A.y_fastest ? t1 : t0;
     const int ty = A.y_fastest ? t0 : t1;
 
-    // each 64-lane wave covers a kWaveX x kWaveY patch of columns
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // each 64-lane wave covers a kWaveX x kWaveY patch of columns (the wave
+    // index is uniform: read it into a scalar register)
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wx0 = tx * kTileX;
     const int wy0 = ty * kTileY + wave * kWaveY;
     const int x = wx0 + (lane % kWaveX);
     const int y = wy0 + (lane / kWaveX);
     const int zl0 = zc * kFusedZ;  // first z of this thread, relative to z_first
-    const float xp = (float)x - A.c;
-    const float yp = (float)y - A.c;
-    const float zp0 = (float)(A.z_first + zl0) - A.c;
-    const float pt = A.y_fastest ? xp : yp;  // transverse and ray coordinates
-    const float pr = A.y_fastest ? yp : xp;
-
-    // Lanes 0..7 hold the corners of the wave's kWaveX x kWaveY x kFusedZ
-    // voxel box.  With w > 0 on the box, every voxel projects inside the
-    // hull of the corner projections, which decides per view whether the
-    // whole wave misses the detector (its taps are all zero: skip the view,
-    // the paper's clipping of Section 3.3) or stays inside the zero border
-    // (no clamping needed).  A 0.5 pixel margin absorbs rounding.
-    const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
-    const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
-    const float czp = zp0 + ((lane & 4) ? (float)(kFusedZ - 1) : 0.0f);
-    const float ctp = A.y_fastest ? cxp : cyp, crp = A.y_fastest ? cyp : cxp;
-    const bool corner_lane = lane < 8;
+    // the part of this wave's box inside the volume (kept in scalar
+    // registers) and this thread's offsets from its centre column
+    BoxFrame bf = box_frame(A, wx0, wy0, A.z_first + zl0, kWaveX, kWaveY, kFusedZ);
+    bf.cx = uniform_f(bf.cx);
+    bf.cy = uniform_f(bf.cy);
+    bf.z0 = uniform_f(bf.z0);
+    bf.hx = uniform_f(bf.hx);
+    bf.hy = uniform_f(bf.hy);
+    bf.hz = uniform_f(bf.hz);
+    const float dx = (float)(lane % kWaveX) - bf.hx;
+    const float dy = (float)(lane / kWaveX) - bf.hy;
+    const float d_t = A.y_fastest ? dx : dy;  // transverse and ray offsets
+    const float d_r = A.y_fastest ? dy : dx;
 
     float acc[kFusedZ];
 #pragma unroll
     for (int i = 0; i < kFusedZ; ++i) acc[i] = 0.0f;
 
+    // The anchors of up to 64 views, one row of 16 words per view, in this
+    // wave's part of LDS: computed one view per lane, then read back per
+    // view at a wave-uniform address (a broadcast), so that they occupy
+    // vector registers only while their view is processed.  Row: uc, vc,
+    // wc, the u and v slopes (transverse, ray, z), the element offset of
+    // pixel (a_u + ku, a_v + kv) in a plane, and the tap index clamp ranges
+    // shifted by the anchor.  (The w row is the folded matrix's, read as
+    // scalars.)
+    __shared__ float anchors[kWgWaves][64][16];
+    float(*an_rows)[16] = anchors[wave];
     const uint32_t plane_bytes = (uint32_t)(A.plane * (long long)kElem);
     const char* plane = (const char*)A.img;
     const const_float* mats = as_constant(A.m);
-    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const const_float* m = mats + 12 * j;
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
-        if constexpr (WCHECK) {
-            accumulate_view<TT, LAYOUT, WCHECK, true, true>(A, m, pt, pr, zp0, rsrc, acc);
-        } else {
-            const float cu = fmaf(czp, m[2], fmaf(m[1], crp, fmaf(m[0], ctp, m[3])));
-            const float cv = fmaf(czp, m[6], fmaf(m[5], crp, fmaf(m[4], ctp, m[7])));
-            const float cw = fmaf(czp, m[10], fmaf(m[9], crp, fmaf(m[8], ctp, m[11])));
-            const float cr = __builtin_amdgcn_rcpf(cw);
-            const float u = cu * cr, v = cv * cr;
-            if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
-                __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
-                continue;
-            accumulate_view<TT, LAYOUT, false, true, VCLAMP>(A, m, pt, pr, zp0, rsrc, acc);
+    for (int j0 = 0; j0 < A.count; j0 += 64) {
+        // lane L: the anchor of view j0 + L; WCHECK batches (some voxel may
+        // have w <= 0) keep a_u = a_v = 0 and skip nothing
+        uint64_t skip;
+        {
+            const Anchor an = make_anchor<!WCHECK>(A, j0 + lane, bf);
+            skip = __ballot(an.skip);
+            const int base = an.av * A.Wp + an.au + A.origin_off;
+            float* row = an_rows[lane];
+            *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
+            *(float4*)(row + 4) = make_float4(an.su_r, an.su2, an.sv_t, an.sv_r);
+            *(float4*)(row + 8) = make_float4(an.sv2, __builtin_bit_cast(float, base),
+                                              __builtin_bit_cast(float, A.lo_iu - an.au),
+                                              __builtin_bit_cast(float, A.hi_iu - an.au));
+            *(int4*)(row + 12) = make_int4(A.lo_iv - an.av, A.hi_iv - an.av, 0, 0);
         }
+        __syncthreads();
+        const int jn = min(64, A.count - j0);
+        for (int jj = 0; jj < jn; ++jj, plane += plane_bytes) {
+            if ((skip >> jj) & 1) continue;
+            // the w row (the same for every box; in the ray frame, as stored)
+            const const_float* m = mats + 12 * (j0 + jj);
+            const float4 r0 = *(const float4*)an_rows[jj];
+            const float4 r1 = *(const float4*)(an_rows[jj] + 4);
+            const int4 r2 = *(const int4*)(an_rows[jj] + 8);
+            const int2 r3 = *(const int2*)(an_rows[jj] + 12);
+            const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
+            accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV>(
+                A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, __builtin_bit_cast(float, r2.x),
+                m[8], m[9], m[10], r2.z, r2.w, r3.x, r3.y, r2.y, d_t, d_r, rsrc, acc);
+        }
+        __syncthreads();  // every wave has read its rows before the next chunk's
     }
 
     if (x < A.N && y < A.N) {
@@ -449,93 +546,115 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     }
 }
 
-template <typename TT, int LAYOUT>
-static void launch_fused_t(const FusedArgs& a, bool wcheck, bool rows_free, hipStream_t s)
+template <typename TT, int LAYOUT, int DIV>
+static void launch_fused_d(const FusedArgs& a, bool wcheck, bool rows_free, hipStream_t s)
 {
     dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
     if (wcheck)
-        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, true, true>), grid, dim3(kThreads), 0, s,
-                           a);
+        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, true, true, DIV>), grid, dim3(kThreads), 0,
+                           s, a);
     else if constexpr (sizeof(typename TT::elem) == 2 && LAYOUT != kRows) {
         if (rows_free)
-            hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, false>), grid, dim3(kThreads),
-                               0, s, a);
+            hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, false, DIV>), grid,
+                               dim3(kThreads), 0, s, a);
         else
-            hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, true>), grid, dim3(kThreads),
-                               0, s, a);
+            hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, true, DIV>), grid,
+                               dim3(kThreads), 0, s, a);
     } else
-        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, true>), grid, dim3(kThreads), 0, s,
-                           a);
+        hipLaunchKernelGGL((bp_fused_kernel<TT, LAYOUT, false, true, DIV>), grid, dim3(kThreads),
+                           0, s, a);
+}
+
+template <typename TT, int LAYOUT>
+static void launch_fused_t(const FusedArgs& a, bool wcheck, bool rows_free, int divide,
+                           hipStream_t s)
+{
+    // the divide variants exist for the default layout only (the host
+    // rejects others)
+    if constexpr (LAYOUT == kDPairs) {
+        if (divide == kDivRcpNR) return launch_fused_d<TT, LAYOUT, kDivRcpNR>(a, wcheck, rows_free, s);
+        if (divide == kDivIEEE) return launch_fused_d<TT, LAYOUT, kDivIEEE>(a, wcheck, rows_free, s);
+        if (divide == kDivRcp12) return launch_fused_d<TT, LAYOUT, kDivRcp12>(a, wcheck, rows_free, s);
+    }
+    launch_fused_d<TT, LAYOUT, kDivRcp>(a, wcheck, rows_free, s);
 }
 
 template <typename TT>
 static void launch_fused_l(const FusedArgs& a, int layout, bool wcheck, bool rows_free,
-                           hipStream_t s)
+                           int divide, hipStream_t s)
 {
     if (layout == kRows)
-        launch_fused_t<TT, kRows>(a, wcheck, false, s);
+        launch_fused_t<TT, kRows>(a, wcheck, false, divide, s);
     else if (layout == kPairs)
-        launch_fused_t<TT, kPairs>(a, wcheck, rows_free, s);
+        launch_fused_t<TT, kPairs>(a, wcheck, rows_free, divide, s);
     else if (layout == kDPairs)
-        launch_fused_t<TT, kDPairs>(a, wcheck, rows_free, s);
+        launch_fused_t<TT, kDPairs>(a, wcheck, rows_free, divide, s);
     else if (layout == kDQuads)
-        launch_fused_t<TT, kDQuads>(a, wcheck, rows_free, s);
+        launch_fused_t<TT, kDQuads>(a, wcheck, rows_free, divide, s);
     else
-        launch_fused_t<TT, kQuads>(a, wcheck, rows_free, s);
+        launch_fused_t<TT, kQuads>(a, wcheck, rows_free, divide, s);
 }
 
 hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, bool rows_free,
-                        hipStream_t s)
+                        int divide, hipStream_t s)
 {
     if (storage == kF32)
-        launch_fused_l<TF32>(a, layout, wcheck, rows_free, s);
+        launch_fused_l<TF32>(a, layout, wcheck, rows_free, divide, s);
     else if (storage == kF16)
-        launch_fused_l<TF16>(a, layout, wcheck, rows_free, s);
+        launch_fused_l<TF16>(a, layout, wcheck, rows_free, divide, s);
     else
-        launch_fused_l<TBF16>(a, layout, wcheck, rows_free, s);
+        launch_fused_l<TBF16>(a, layout, wcheck, rows_free, divide, s);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // plain
 // ---------------------------------------------------------------------------
+// Pixel (column j, row k) of an unpadded H x W view, zero outside it (the
+// zero extension of Section 3.3, here by a bounds test per tap).
+__device__ __forceinline__ float zero_extended(const float* view, int W, int H, int j, int k)
+{
+    return ((unsigned)j < (unsigned)W && (unsigned)k < (unsigned)H) ? view[(size_t)k * W + j]
+                                                                     : 0.0f;
+}
+
 __global__ __launch_bounds__(256) void bp_plain_kernel(const PlainArgs A)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= A.N || y >= A.N) return;
-    const float wx = A.ox + (float)x * A.vs;
-    const float wy = A.oy + (float)y * A.vs;
-    const float wz = A.oz + (float)z * A.vs;
+    // world coordinates of the voxel centre (mm)
+    const float X = A.ox + (float)x * A.vs;
+    const float Y = A.oy + (float)y * A.vs;
+    const float Z = A.oz + (float)z * A.vs;
     const int H = A.H, W = A.W;
     float sum = 0.0f;
-    const float* I = A.proj;
-    for (int j = 0; j < A.count; ++j, I += (size_t)H * W) {
+    const float* view = A.proj;
+    for (int j = 0; j < A.count; ++j, view += (size_t)H * W) {
         const float* m = A.m[j];
-        const float uw = m[0] * wx + m[1] * wy + m[2] * wz + m[3];
-        const float vw = m[4] * wx + m[5] * wy + m[6] * wz + m[7];
-        const float w = m[8] * wx + m[9] * wy + m[10] * wz + m[11];
+        // part 1: homogeneous detector coordinates and two IEEE divisions
+        const float uw = m[0] * X + m[1] * Y + m[2] * Z + m[3];
+        const float vw = m[4] * X + m[5] * Y + m[6] * Z + m[7];
+        const float w = m[8] * X + m[9] * Y + m[10] * Z + m[11];
         if (!(w > 0.0f)) continue;
         const float u = uw / w;
         const float v = vw / w;
-        if (!(u > -2.0f && u < (float)W + 1.0f && v > -2.0f && v < (float)H + 1.0f)) continue;
+        // a sample left of column -1 or right of column W - 1 (likewise
+        // rows) has all four taps outside the view: nothing to add
+        if (!(u >= -1.0f && u < (float)W && v >= -1.0f && v < (float)H)) continue;
+        // part 2: the four zero-extended neighbours of (u, v)
         const float fu = floorf(u), fv = floorf(v);
-        const int iu = (int)fu, iv = (int)fv;
-        const float scalx = u - fu, scaly = v - fv;
-        float valtl = 0.0f, valtr = 0.0f, valbl = 0.0f, valbr = 0.0f;
-        if (iv >= 0 && iv < H) {
-            if (iu >= 0 && iu < W) valtl = I[iv * W + iu];
-            if (iu >= -1 && iu < W - 1) valtr = I[iv * W + iu + 1];
-        }
-        if (iv >= -1 && iv < H - 1) {
-            if (iu >= 0 && iu < W) valbl = I[(iv + 1) * W + iu];
-            if (iu >= -1 && iu < W - 1) valbr = I[(iv + 1) * W + iu + 1];
-        }
-        const float vall = scaly * valbl + (1.0f - scaly) * valtl;
-        const float valr = scaly * valbr + (1.0f - scaly) * valtr;
-        const float fx = scalx * valr + (1.0f - scalx) * vall;
-        sum += 1.0f / (w * w) * fx;
+        const int c0 = (int)fu, r0 = (int)fv;
+        const float p00 = zero_extended(view, W, H, c0, r0);
+        const float p10 = zero_extended(view, W, H, c0 + 1, r0);
+        const float p01 = zero_extended(view, W, H, c0, r0 + 1);
+        const float p11 = zero_extended(view, W, H, c0 + 1, r0 + 1);
+        // part 3: two horizontal lerps, one vertical, weight 1/w^2
+        const float a = u - fu, b = v - fv;
+        const float upper = fmaf(a, p10 - p00, p00);
+        const float lower = fmaf(a, p11 - p01, p01);
+        sum = fmaf(fmaf(b, lower - upper, upper), 1.0f / (w * w), sum);
     }
     A.vol[((size_t)z * A.N + y) * A.N + x] += sum;
 }
@@ -552,7 +671,10 @@ hipError_t launch_plain(const PlainArgs& a, hipStream_t s)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void put_mats_kernel(const PutMatsArgs a)
 {
-    for (int i = threadIdx.x; i < 12 * a.count; i += 256) a.dst[i] = a.m[i];
+    for (int i = threadIdx.x; i < 12 * a.count; i += 256) {
+        a.dst[i] = a.m[i];
+        a.dstq[i] = a.q[i];
+    }
 }
 
 hipError_t launch_put_mats(const PutMatsArgs& a, hipStream_t s)

@@ -68,7 +68,14 @@ struct FusedArgs {
     const float* m;      // count x 12 folded matrices of this batch (device memory), in
                          // the ray frame: column 0 multiplies the transverse coordinate
                          // (x if y_fastest, else y), column 1 the ray coordinate
-    int fp_tile;         // forward projection: entries of a workgroup's LDS tile
+    const double* mq;    // the same matrices in FP64 before rounding, columns x, y, z, 1
+    int lo_iu, hi_iu;    // clamp range of the tap index floor(u') (zero border included)
+    int lo_iv, hi_iv;
+    // forward projection
+    int fp_tile;                   // entries of a workgroup's LDS tile
+    unsigned long long* acc64;     // count padded planes of 64-bit fixed-point sums
+    const unsigned* fp_vmax;       // max |x| of the volume (float bits, device)
+    float fp_rmax2;                // >= 1 / w^2 over the volume and the batch's views
 };
 
 // Arguments of the plain kernel: world-coordinate matrices (FP32 roundings
@@ -82,14 +89,16 @@ struct PlainArgs {
     float m[kPlainBatch][12];
 };
 
-// A batch's folded matrices carried in the kernel arguments, written to
-// device memory by a one-block kernel (used where the library may not copy
-// them from pinned host memory).
-constexpr int kPutMatsMax = 64;
+// Folded matrices carried in the kernel arguments (under their 4 KiB
+// limit), written to device memory by a one-block kernel (used where the
+// library may not copy them from pinned host memory).
+constexpr int kPutMatsMax = 24;
 struct PutMatsArgs {
     float* dst;          // count x 12 floats
+    double* dstq;        // count x 12 doubles
     int count;           // <= kPutMatsMax
     float m[kPutMatsMax * 12];
+    double q[kPutMatsMax * 12];
 };
 
 struct StageArgs {
@@ -100,12 +109,17 @@ struct StageArgs {
     int layout;
 };
 
-// Padded FP32 accumulation planes of the forward projector (rows layout).
+// Padded 64-bit fixed-point accumulation planes of the forward projector
+// (rows layout), in units of 2^-kg with kg from (N, *vmax, rmax2).
 struct UnstageArgs {
-    const float* planes;  // count planes of Hp*Wp floats, pixel (j, k) at (k+kPad)*Wp + j+kPad
-    float* dst;           // count views of H*W floats, accumulated
+    const unsigned long long* planes;  // count planes of Hp*Wp, pixel (j, k) at (k+kPad)*Wp + j+kPad
+    float* dst;                        // count views of H*W floats, accumulated
     int H, W, Hp, Wp;
     int count;
+    int fixed;                         // 1: 64-bit fixed point; 0: float planes
+    int N;
+    const unsigned* vmax;
+    float rmax2;
 };
 
 
@@ -113,9 +127,15 @@ struct UnstageArgs {
 hipError_t launch_stage(const StageArgs& a, int storage, hipStream_t s);
 // rows_free: v is not clamped (only with !wcheck and a single-load layout;
 // the host has bounded every tap row, see rows_bounded)
+// divide: the reciprocal variant of part 1 (0 v_rcp_f32, 1 rcp + one Newton
+// step, 2 IEEE divisions, 3 rcp truncated to 12 bits); non-zero only with
+// the dpairs layout
 hipError_t launch_fused(const FusedArgs& a, int storage, int layout, bool wcheck, bool rows_free,
-                        hipStream_t s);
+                        int divide, hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, hipStream_t s);
+// FP32 stack -> FP16 (per-view powers of 4 written to view_scale, device) or BF16
+hipError_t launch_convert(void* dst, const float* src, int n_views, size_t view_len, int storage,
+                          float* view_scale, hipStream_t s);
 hipError_t launch_update_probe(float* a, size_t n, float s, hipStream_t st);
 hipError_t launch_put_mats(const PutMatsArgs& a, hipStream_t s);
 hipError_t launch_zero(float* a, size_t n, hipStream_t st);
@@ -124,6 +144,8 @@ hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s);
 // as launch_scatter for w > 0 everywhere; tiles of 16 x 16 columns
 hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s);
 hipError_t launch_unstage_add(const UnstageArgs& a, hipStream_t s);
+// max |x| over n floats as float bits into *out (which must hold 0 before)
+hipError_t launch_fp_vmax(const float* vol, size_t n, unsigned* out, hipStream_t s);
 
 // z voxels per thread: the forward projection kernels, and the fused
 // backprojection by storage type (FP32 taps: 16; 16-bit taps: 8, whose

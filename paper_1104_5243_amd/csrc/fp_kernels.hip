@@ -1,20 +1,104 @@
 // Forward projection kernels for gfx950: the exact transpose of the fused
-// backprojection, used as its adjoint (gradients through the backprojection)
-// and as a matched projector.
+// backprojection (FP32 storage, default reciprocal), used as its adjoint
+// (gradients through the backprojection) and as a matched projector.
+//
+// Every voxel value times r^2 = 1/w^2 is spread onto the four taps the
+// backprojection reads for that (voxel, view) pair, with the same bilinear
+// weights (1-au)(1-av), au(1-av), (1-au)av, au av: both kernels take the
+// pair's coordinates from the same anchored geometry (anchor.h), with the
+// same boxes and the same operations in the same order, so they agree bit
+// for bit.  Taps outside the detector land in the 2-pixel border of padded
+// planes and are dropped when the interior is added to the caller's stack.
+//
+// The planes hold 64-bit fixed-point sums: integer additions do not depend
+// on their order, so the result is the same on every run.  One scale 2^kg
+// per launch, from a bound on any plane sum: the bilinear weights of a
+// voxel sum to 1, so a pixel receives at most B = sum |x| r^2 <= N^3 max|x|
+// max r^2, and kg keeps B 2^kg below 2^60 (fp_global_exponent).  Each
+// contribution is rounded to a multiple of 2^-kg (far below FP32's
+// resolution of the sums).
+#include "anchor.h"
 #include "fdk_internal.h"
 #include "gfx950_util.h"
 
 namespace fdk {
 
+static_assert(kFpZ == fused_z(kF32), "forward projection boxes are the FP32 backprojection's");
+
+// kg for a launch: N^3 * vmax * rmax2 * 2^kg < 2^60 (a factor 2 of margin
+// over the float rounding of the bound); 0 if there is nothing to project.
+__device__ __forceinline__ int fp_global_exponent(int N, float vmax, float rmax2)
+{
+    const float bound = (float)N * (float)N * (float)N * vmax * rmax2;
+    if (!(bound > 0.0f) || !(bound < 1.0e38f)) return 0;
+    int e;
+    frexpf(bound, &e);  // bound < 2^e
+    return min(max(60 - e, -120), 120);
+}
+
+// x rounded to the nearest integer, ties towards +infinity (one instruction)
+__device__ __forceinline__ int cvt_nearest(float x)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// A tap value already scaled by 2^kg (|x| < 2^60) as a 64-bit integer,
+// rounded to nearest.
+__device__ __forceinline__ unsigned long long to_fixed64(float x)
+{
+    return (unsigned long long)__float2ll_rn(x);
+}
+
+__device__ __forceinline__ void add64(unsigned long long* p, unsigned long long v)
+{
+    if (v) atomicAdd(p, v);
+}
+
+// The four taps of one voxel, scaled by 2^kg, added to a padded plane at
+// element `off` (top-left tap) with row pitch Wp.
+__device__ __forceinline__ void scatter_taps64(unsigned long long* plane, uint32_t off, int Wp,
+                                               float s, float au, float av)
+{
+    const float b = s * av;  // bottom row weight
+    const float a = s - b;   // top row weight
+    const float tr = a * au, br = b * au;
+    add64(plane + off, to_fixed64(a - tr));
+    add64(plane + off + 1, to_fixed64(tr));
+    add64(plane + off + Wp, to_fixed64(b - br));
+    add64(plane + off + Wp + 1, to_fixed64(br));
+}
+
+// Largest |x| of the volume as the bits of a non-negative float (whose
+// integer order is the float order), merged into *out (zeroed before).
+__global__ __launch_bounds__(256) void fp_vmax_kernel(const float* vol, size_t n, unsigned* out)
+{
+    float m = 0.0f;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+        m = fmaxf(m, fabsf(vol[i]));
+    for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+hipError_t launch_fp_vmax(const float* vol, size_t n, unsigned* out, hipStream_t s)
+{
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(fp_vmax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, vol, n, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// forward projection: the exact transpose of the backprojection
+// scatter: the backprojection's workgroups, waves and boxes, 64-bit atomics
 // ---------------------------------------------------------------------------
-// Every voxel value times r^2 = 1/w^2 is spread onto the four taps the
-// backprojection reads, with the same bilinear weights (1-au)(1-av), au(1-av),
-// (1-au)av, au av.  The targets are padded FP32 planes (rows layout): taps
-// outside the detector land in the 2-pixel border and are dropped when the
-// interior is added to the caller's stack.  Float atomics make the order of
-// the sums, and so their last bits, vary between runs.
+// One thread per column and kFpZ slices of a wave's 8 x 8 x kFpZ box, as the
+// backprojection; each voxel's four taps go straight to the plane.  Used for
+// batches where some voxel may have w <= 0 (no anchor, as the
+// backprojection there; float planes, since 1/w^2 has no bound) and when the
+// LDS kernel is switched off (64-bit planes).
 template <bool WCHECK>
 __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
 {
@@ -25,26 +109,22 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
     }
     const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
     const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
-    const int t1 = rest % (A.y_fastest ? A.tiles_x : A.tiles_y);
-    const int zc = rest / (A.y_fastest ? A.tiles_x : A.tiles_y);
+    const int zc = rest % A.zchunks;
+    const int t1 = rest / A.zchunks;
     const int tx = A.y_fastest ? t1 : t0;
     const int ty = A.y_fastest ? t0 : t1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wx0 = tx * kTileX;
     const int wy0 = ty * kTileY + wave * kWaveY;
     const int x = wx0 + (lane % kWaveX);
     const int y = wy0 + (lane / kWaveX);
     const int zl0 = zc * kFpZ;
-    const float xp = (float)x - A.c;
-    const float yp = (float)y - A.c;
-    const float zp0 = (float)(A.z_first + zl0) - A.c;
-    const float cxp = (float)(wx0 + ((lane & 1) ? kWaveX - 1 : 0)) - A.c;
-    const float cyp = (float)(wy0 + ((lane & 2) ? kWaveY - 1 : 0)) - A.c;
-    const float czp = zp0 + ((lane & 4) ? (float)(kFpZ - 1) : 0.0f);
-    // transverse and ray coordinates (the matrices are in the ray frame)
-    const float ctp = A.y_fastest ? cxp : cyp, crp = A.y_fastest ? cyp : cxp;
-    const float pt = A.y_fastest ? xp : yp, pr = A.y_fastest ? yp : xp;
-    const bool corner_lane = lane < 8;
+    BoxFrame bf = box_frame(A, wx0, wy0, A.z_first + zl0, kWaveX, kWaveY, kFpZ);
+    const float dx = (float)(lane % kWaveX) - bf.hx;
+    const float dy = (float)(lane / kWaveX) - bf.hy;
+    const float d_t = A.y_fastest ? dx : dy;
+    const float d_r = A.y_fastest ? dy : dx;
 
     // the thread's voxel values (0 outside the volume)
     float val[kFpZ];
@@ -55,54 +135,65 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
     for (int i = 0; i < kFpZ; ++i)
         val[i] = (inside && zl0 + i < A.nz) ? src[(size_t)i * slice] : 0.0f;
 
+    const int kg = fp_global_exponent(A.N, __uint_as_float(*A.fp_vmax), A.fp_rmax2);
+    const float Sg = __builtin_ldexpf(1.0f, kg);
     const int Wp = A.Wp;
-    const uint32_t row_bytes = (uint32_t)Wp * 4u;
-    const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
-    const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
-    const char* plane = (const char*)A.img;
+    __shared__ float anchors[kWgWaves][64][16];
+    float(*an_rows)[16] = anchors[wave];
+    unsigned long long* plane = A.acc64;
     const const_float* mats = as_constant(A.m);
-    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const const_float* m = mats + 12 * j;
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
-        if constexpr (!WCHECK) {
-            const float cu = fmaf(czp, m[2], fmaf(m[1], crp, fmaf(m[0], ctp, m[3])));
-            const float cv = fmaf(czp, m[6], fmaf(m[5], crp, fmaf(m[4], ctp, m[7])));
-            const float cw = fmaf(czp, m[10], fmaf(m[9], crp, fmaf(m[8], ctp, m[11])));
-            const float cr = __builtin_amdgcn_rcpf(cw);
-            const float u = cu * cr, v = cv * cr;
-            if (__all(!corner_lane || u < A.skip_lo_u) || __all(!corner_lane || u > A.skip_hi_u) ||
-                __all(!corner_lane || v < A.skip_lo_v) || __all(!corner_lane || v > A.skip_hi_v))
-                continue;
+    for (int j0 = 0; j0 < A.count; j0 += 64) {
+        uint64_t skip;
+        {
+            const Anchor an = make_anchor<!WCHECK>(A, j0 + lane, bf);
+            skip = __ballot(an.skip);
+            float* row = an_rows[lane];
+            *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
+            *(float4*)(row + 4) = make_float4(an.su_r, an.su2, an.sv_t, an.sv_r);
+            *(float4*)(row + 8) =
+                make_float4(an.sv2, __builtin_bit_cast(float, an.av * Wp + an.au + A.origin_off),
+                            __builtin_bit_cast(float, A.lo_iu - an.au),
+                            __builtin_bit_cast(float, A.hi_iu - an.au));
+            *(int4*)(row + 12) = make_int4(A.lo_iv - an.av, A.hi_iv - an.av, 0, 0);
         }
-        // the column base in the backprojection's order: the transverse
-        // term first, then the ray term
-        const float bu = fmaf(m[1], pr, fmaf(m[0], pt, m[3]));
-        const float bv = fmaf(m[5], pr, fmaf(m[4], pt, m[7]));
-        const float bw = fmaf(m[9], pr, fmaf(m[8], pt, m[11]));
+        __syncthreads();
+        const int jn = min(64, A.count - j0);
+        for (int jj = 0; jj < jn; ++jj, plane += A.plane) {
+            if ((skip >> jj) & 1) continue;
+            const const_float* m = mats + 12 * (j0 + jj);
+            const float4 r0 = *(const float4*)an_rows[jj];
+            const float4 r1 = *(const float4*)(an_rows[jj] + 4);
+            const int4 r2 = *(const int4*)(an_rows[jj] + 8);
+            const int2 r3 = *(const int2*)(an_rows[jj] + 12);
+            float bu, bv, bw;
+            column_base(r0.x, r0.y, r0.z, r0.w, r1.x, r1.z, r1.w, m[8], m[9], d_t, d_r, bu, bv,
+                        bw);
+            const float su2 = r1.y, sv2 = __builtin_bit_cast(float, r2.x), sw2 = m[10];
 #pragma unroll
-        for (int i = 0; i < kFpZ; ++i) {
-            const float zp = zp0 + (float)i;
-            const float uw = fmaf(zp, m[2], bu);
-            const float vw = fmaf(zp, m[6], bv);
-            const float w = fmaf(zp, m[10], bw);
-            float r = __builtin_amdgcn_rcpf(w);
-            if (WCHECK) r = (w > 0.0f) ? r : 0.0f;
-            const float u = uw * r;
-            const float v = vw * r;
-            const float au = __builtin_amdgcn_fractf(u);
-            const float av = __builtin_amdgcn_fractf(v);
-            const int iu = cvt_floor(__builtin_amdgcn_fmed3f(u, A.lo_u, A.hi_u));
-            const int iv = cvt_floor(__builtin_amdgcn_fmed3f(v, A.lo_v, A.hi_v));
-            const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
-            const float s = val[i] * (r * r);
-            const float b = s * av;       // bottom row weight
-            const float a = s - b;        // top row weight
-            const float tr = a * au, br = b * au;
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b - br, rsrc, off, row_bytes, 0);
-            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(br, rsrc, off + 4u, row_bytes, 0);
+            for (int i = 0; i < kFpZ; ++i) {
+                float u, v, r;
+                voxel_coords<kDivRcp, WCHECK>(bu, bv, bw, su2, sv2, sw2, (float)i, u, v, r);
+                const float au = __builtin_amdgcn_fractf(u);
+                const float av = __builtin_amdgcn_fractf(v);
+                const int ju = med3_i32(cvt_floor(u), r2.z, r2.w);
+                const int jv = med3_i32(cvt_floor(v), r3.x, r3.y);
+                const uint32_t off = (uint32_t)(mad_i24_ub(jv, Wp, ju) + r2.y);
+                if constexpr (WCHECK) {
+                    // w may come arbitrarily close to 0 (no fixed-point bound):
+                    // float sums, whose last bits depend on the atomics' order
+                    float* fp = (float*)plane;
+                    const float s = val[i] * (r * r);
+                    const float b = s * av, a = s - b, tr = a * au, br = b * au;
+                    atomicAdd(fp + off, a - tr);
+                    atomicAdd(fp + off + 1, tr);
+                    atomicAdd(fp + off + Wp, b - br);
+                    atomicAdd(fp + off + Wp + 1, br);
+                } else {
+                    scatter_taps64(plane, off, Wp, val[i] * (r * r) * Sg, au, av);
+                }
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -116,48 +207,55 @@ hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
     return hipGetLastError();
 }
 
-// LDS variant of the forward projection.  A workgroup owns a 16 x 16 x 16
-// voxel box.  Per view the 8 projected box corners bound the box's
-// footprint on the detector (the projection of the box lies in the hull of
-// the corners); the workgroup accumulates its scatter into an LDS tile
-// covering that footprint (plus a 1-pixel margin against rounding) and then
-// adds the tile's non-zero pixels to the padded plane with one global
-// atomic each: about one global atomic per footprint pixel instead of four
-// per voxel.  A footprint larger than the tile falls back to direct global
-// atomics for that view.
+// ---------------------------------------------------------------------------
+// LDS tiles
+// ---------------------------------------------------------------------------
+// A workgroup owns a 16 x 16 x 16 voxel box: 2 x 2 of the backprojection's
+// 8 x 8 x 16 boxes.  Per view the boxes' projected intervals bound the
+// workgroup's footprint on the detector; the workgroup accumulates its
+// scatter into an LDS tile covering that footprint (plus a 1-pixel margin)
+// and then adds the tile's non-zero pixels to the padded plane with one
+// 64-bit atomic each: about one global atomic per footprint pixel instead of
+// four per voxel.  A footprint larger than the tile takes the 64-bit
+// atomics per tap for that view.
 //
 // The tile accumulates in 32-bit fixed point with integer LDS atomics
 // (float LDS atomics measured ~40x slower than integer ones on this GPU).
-// Per view the scale is a power of two S with 4096 * max|x| * max r^2 * S
-// below 2^31, where max|x| is the largest voxel value of the box and max r^2
-// = 1 / min w^2 over the box corners: a pixel receives at most one tap of
-// each of the box's 4096 voxels and each tap is at most |x| r^2, so no tile
-// sum can overflow.  Each tap is rounded to the nearest multiple of 1/S
-// (error <= 2^-32 * 4096 * max|x| * max r^2 per tap); the tile sums are then
-// exact, independent of the order of the atomics.
+// Per view the tile's scale is a power of two St with 4096 * max|x| * max r^2
+// * St below 2^31, where max|x| is the largest voxel value of the workgroup's
+// box and max r^2 = 1 / (min w)^2 over it: a pixel receives at most one tap
+// of each of the box's 4096 voxels and each tap is at most |x| r^2, so no
+// tile sum can overflow.  Each tap is rounded to the nearest multiple of
+// 1/St; a tile sum is then exact, and its conversion to the plane's scale
+// (a shift) is exact or rounds once.
 constexpr int kFpTile = 16;
+constexpr int kFpChunk = 16;  // views whose anchors are computed together
 
-// x rounded to the nearest integer, ties towards +infinity (one instruction)
-__device__ __forceinline__ int cvt_nearest(float x)
-{
-    int r;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
-// waves per SIMD the registers are fitted to (up to 128 VGPRs).  Five 32 KiB
-// tiles would fit the 160 KiB of LDS of a CU, but fitting the kernel to 5
-// waves (96 VGPRs) spills: 256^3 x 248 views took 3.46 ms against 2.85 ms.
+// waves per SIMD the registers are fitted to (up to 128 VGPRs)
 #ifndef FDK_FP_WAVES
 #define FDK_FP_WAVES 4
 #endif
+
+// A tile sum t in units of 2^-kt, in units of 2^-kg (rounded to nearest,
+// ties up, where kg < kt).
+__device__ __forceinline__ unsigned long long rescale_fixed(int t, int kt, int kg)
+{
+    const int sh = kg - kt;
+    const long long v = t;
+    if (sh >= 0) return (unsigned long long)(v << sh);
+    if (sh < -32) return 0ull;  // |t| < 2^31: below half a unit
+    return (unsigned long long)((v + (1ll << (-sh - 1))) >> (-sh));
+}
+
 template <bool ALONG_Y>
 __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedArgs A)
 {
-    // A.fp_tile tile entries at LDS address 0; the first 4 hold the wave
-    // maxima of the box's values before the first view
-    extern __shared__ int tile[];
-    float* wave_max = (float*)tile;
+    extern __shared__ int tile[];  // A.fp_tile entries
+    // anchors (16 words) and projected bounds (8 words) of the 4 boxes for a
+    // chunk of views, and the waves' largest |x|
+    __shared__ float rows[4][kFpChunk][16];
+    __shared__ float bnds[4][kFpChunk][8];
+    __shared__ float wave_max[4];
     int bid = blockIdx.x;
     if (A.xcd_remap) {
         const int per = gridDim.x >> 3;
@@ -170,31 +268,20 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     const int t1 = rest / A.zchunks;
     const int tx = A.y_fastest ? t1 : t0;
     const int ty = A.y_fastest ? t0 : t1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int bx0 = tx * kFpTile, by0 = ty * kFpTile;
-    const int zl0 = zc * kFpZ;
+    const int zl0 = zc * kFpZ, zs0 = A.z_first + zl0;
     // A thread owns the 16 voxels of the box along the axis closest to the
-    // batch's rays (y if y_fastest, else x); the lanes of a wave span the
-    // other horizontal axis (16) and 4 z.  Voxels along a ray project onto
-    // the same pixels: this way they fall to one thread, one after the
+    // batch's rays (y if ALONG_Y, else x); the lanes of a wave span the
+    // other horizontal axis (16) and 4 slices.  Voxels along a ray project
+    // onto the same pixels: this way they fall to one thread, one after the
     // other, and the 64 lanes of an atomic instruction hit 64 distinct
     // places (transverse neighbours ~2 px apart, z neighbours ~2 rows).
     const int tt = threadIdx.x & 15, zz = threadIdx.x >> 4;
-    constexpr bool along_y = ALONG_Y;  // == (A.y_fastest != 0)
-    const int x = along_y ? bx0 + tt : bx0;  // first voxel of the thread's line
-    const int y = along_y ? by0 : by0 + tt;
-    const int z = A.z_first + zl0 + zz;
-    const float xp = (float)x - A.c;
-    const float yp = (float)y - A.c;
-    const float zp = (float)z - A.c;
-    // lanes 0..7 of every wave hold the corners of the workgroup's box
-    const float cxp = (float)(bx0 + ((lane & 1) ? kFpTile - 1 : 0)) - A.c;
-    const float cyp = (float)(by0 + ((lane & 2) ? kFpTile - 1 : 0)) - A.c;
-    const float czp = (float)(A.z_first + zl0) - A.c + ((lane & 4) ? (float)(kFpZ - 1) : 0.0f);
-    // transverse and ray coordinates (the matrices are in the ray frame)
-    const float ctp = along_y ? cxp : cyp, crp = along_y ? cyp : cxp;
-    const float pt = along_y ? xp : yp, pr0 = along_y ? yp : xp;
-    const bool corner_lane = lane < 8;
+    const int x = ALONG_Y ? bx0 + tt : bx0;  // first voxel of the thread's line
+    const int y = ALONG_Y ? by0 : by0 + tt;
+    const int z = zs0 + zz;
 
     float val[kFpTile];
     const size_t slice = (size_t)A.N * A.N;
@@ -206,7 +293,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     float vmax = 0.0f;
 #pragma unroll
     for (int i = 0; i < kFpTile; ++i) {
-        const int xi = along_y ? x : x + i, yi = along_y ? y + i : y;
+        const int xi = ALONG_Y ? x : x + i, yi = ALONG_Y ? y + i : y;
         const float v = src[(size_t)min(yi, A.N - 1) * A.N + min(xi, A.N - 1)];
         val[i] = (zin && xi < A.N && yi < A.N) ? v : 0.0f;
         vmax = fmaxf(vmax, fabsf(val[i]));
@@ -217,142 +304,153 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     __syncthreads();
     vmax = fmaxf(fmaxf(wave_max[0], wave_max[1]), fmaxf(wave_max[2], wave_max[3]));
     if (vmax == 0.0f) return;  // nothing to project (uniform over the block)
-    __syncthreads();           // every wave has read wave_max before the tile is zeroed
 
+    // the thread's two boxes along its line (b = bx + 2 by) and its offsets
+    const int tb = tt >> 3;
+    int box[2];
+    float d_t[2], h_r[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        box[h] = ALONG_Y ? (tb + 2 * h) : (h + 2 * tb);
+        const BoxFrame f = box_frame(A, bx0 + 8 * (box[h] & 1), by0 + 8 * (box[h] >> 1), zs0,
+                                     kWaveX, kWaveY, kFpZ);
+        d_t[h] = (float)(tt & 7) - (ALONG_Y ? f.hx : f.hy);
+        h_r[h] = ALONG_Y ? f.hy : f.hx;
+    }
+
+    const int kg = fp_global_exponent(A.N, __uint_as_float(*A.fp_vmax), A.fp_rmax2);
+    const float Sg = __builtin_ldexpf(1.0f, kg);
     const int Wp = A.Wp;
-    const uint32_t row_bytes = (uint32_t)Wp * 4u;
-    const uint32_t plane_bytes = (uint32_t)(A.plane * 4ll);
-    const uint32_t centre_bytes = (uint32_t)A.origin_off * 4u;
-    const int lo_u = (int)A.lo_u, hi_u = (int)(A.hi_u - 0.5f);
-    const int lo_v = (int)A.lo_v, hi_v = (int)(A.hi_v - 0.5f);
-    const char* plane = (const char*)A.img;
     const const_float* mats = as_constant(A.m);
-    for (int j = 0; j < A.count; ++j, plane += plane_bytes) {
-        const const_float* m = mats + 12 * j;
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
-        const float cu = fmaf(czp, m[2], fmaf(m[1], crp, fmaf(m[0], ctp, m[3])));
-        const float cv = fmaf(czp, m[6], fmaf(m[5], crp, fmaf(m[4], ctp, m[7])));
-        const float cw = fmaf(czp, m[10], fmaf(m[9], crp, fmaf(m[8], ctp, m[11])));
-        const float cr = __builtin_amdgcn_rcpf(cw);
-        float umin = corner_lane ? cu * cr : INFINITY, umax = corner_lane ? cu * cr : -INFINITY;
-        float vmin = corner_lane ? cv * cr : INFINITY, vmx = corner_lane ? cv * cr : -INFINITY;
-        float wmin = corner_lane ? cw : INFINITY;
-#pragma unroll
-        for (int d = 1; d < 8; d <<= 1) {
-            umin = fminf(umin, __shfl_xor(umin, d));
-            umax = fmaxf(umax, __shfl_xor(umax, d));
-            vmin = fminf(vmin, __shfl_xor(vmin, d));
-            vmx = fmaxf(vmx, __shfl_xor(vmx, d));
-            wmin = fminf(wmin, __shfl_xor(wmin, d));
+    unsigned long long* plane = A.acc64;
+    for (int j0 = 0; j0 < A.count; j0 += kFpChunk, plane += kFpChunk * A.plane) {
+        if (threadIdx.x < 4 * kFpChunk) {
+            // thread (b, view): the anchor of box b for view j0 + view
+            const int b = threadIdx.x / kFpChunk, jv = threadIdx.x % kFpChunk;
+            const BoxFrame f = box_frame(A, bx0 + 8 * (b & 1), by0 + 8 * (b >> 1), zs0, kWaveX,
+                                         kWaveY, kFpZ);
+            const Anchor an = make_anchor<true>(A, j0 + jv, f);
+            float* row = rows[b][jv];
+            *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
+            *(float4*)(row + 4) = make_float4(an.su_r, an.su2, an.sv_t, an.sv_r);
+            *(float4*)(row + 8) = make_float4(an.sv2, __builtin_bit_cast(float, an.au),
+                                              __builtin_bit_cast(float, an.av), 0.0f);
+            // a skipped box takes no part in the footprint
+            const bool part = !an.skip;
+            *(float4*)bnds[b][jv] = make_float4(part ? an.umin : INFINITY,
+                                                part ? an.umax : -INFINITY,
+                                                part ? an.vmin : INFINITY,
+                                                part ? an.vmax : -INFINITY);
+            *(float4*)(bnds[b][jv] + 4) = make_float4(part ? an.wmin : INFINITY,
+                                                      part ? 1.0f : 0.0f, 0.0f, 0.0f);
         }
-        umin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umin)));
-        umax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(umax)));
-        vmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmin)));
-        vmx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vmx)));
-        wmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmin)));
-        // every wave computed the same corners: the decisions below agree
-        if (umax < A.skip_lo_u || umin > A.skip_hi_u || vmx < A.skip_lo_v || vmin > A.skip_hi_v)
-            continue;
-        const int U0 = max((int)floorf(umin) - 1, lo_u);
-        const int U1 = min((int)floorf(umax) + 2, hi_u + 1);
-        const int V0 = max((int)floorf(vmin) - 1, lo_v);
-        const int V1 = min((int)floorf(vmx) + 2, hi_v + 1);
-        const int TW = U1 - U0 + 1, TH = V1 - V0 + 1;
-        // fixed-point scale: 4096 * vmax * rmax^2 * S < 2^31 (see above);
-        // one binade of margin against the rounding of the bound.  Bounds
-        // outside [1e-20, 1e30] (or not finite) take the float path.
-        const float rmax = 1.0f / wmin;
-        const float bound = 4096.0f * vmax * rmax * rmax;
-        const bool use_lds = TW * TH <= A.fp_tile && bound >= 1e-20f && bound <= 1e30f;
-        const int k = min(max((int)floorf(__builtin_log2f(2147483648.0f / bound)) - 1, -100), 100);
-        const float S = __builtin_ldexpf(1.0f, k), invS = __builtin_ldexpf(1.0f, -k);
-        if (use_lds) {
-            for (int e = threadIdx.x; e < TW * TH; e += 256) tile[e] = 0;
-            __syncthreads();
-        }
-        // (u'w, v'w, w) of voxel i of the line, rounded exactly as the fused
-        // backprojection rounds them (the transverse axis's term, then the
-        // ray axis's, then z), so that both operators see the same
-        // coordinates for every pair; the transverse term is the line's
-        // constant.  Then the fractions, the tap indices of the coordinates
-        // clamped to [lo, hi], and the weighted value r^2 x.
-        const float tu = fmaf(m[0], pt, m[3]);
-        const float tv = fmaf(m[4], pt, m[7]);
-        const float tw = fmaf(m[8], pt, m[11]);
-        auto voxel = [&](int i, float lo_u, float hi_u, float lo_v, float hi_v, float& au,
-                         float& av, int& iu, int& iv, float& s) {
-            const float pr = pr0 + (float)i;
-            const float uw = fmaf(zp, m[2], fmaf(m[1], pr, tu));
-            const float vw = fmaf(zp, m[6], fmaf(m[5], pr, tv));
-            const float w = fmaf(zp, m[10], fmaf(m[9], pr, tw));
-            const float r = __builtin_amdgcn_rcpf(w);
-            const float u = uw * r;
-            const float v = vw * r;
-            au = __builtin_amdgcn_fractf(u);
-            av = __builtin_amdgcn_fractf(v);
-            iu = cvt_floor(__builtin_amdgcn_fmed3f(u, lo_u, hi_u));
-            iv = cvt_floor(__builtin_amdgcn_fmed3f(v, lo_v, hi_v));
-            s = val[i] * (r * r);
-        };
-        if (use_lds) {
-            // Tap (iu, iv) at tile index (iv - V0) TW + (iu - U0).  Clamping u
-            // to [U0, U1 - 0.5] and v to [V0, V1 - 0.5] keeps all four taps
-            // inside the tile; it changes no tap: the box projects inside
-            // [umin, umax] x [vmin, vmax], one pixel inside the tile, except
-            // where U0 = lo_u or U1 = hi_u + 1 (likewise v), and there it is
-            // the clamp to the padded plane's border that every path applies.
-            const int base = -(V0 * TW + U0);
-            const float cu0 = (float)U0, cu1 = (float)U1 - 0.5f;
-            const float cv0 = (float)V0, cv1 = (float)V1 - 0.5f;
+        __syncthreads();
+        const int jn = min(kFpChunk, A.count - j0);
+        for (int jj = 0; jj < jn; ++jj) {
+            unsigned long long* pl = plane + (size_t)jj * A.plane;
+            // footprint of the boxes that reach the detector
+            float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmx = -INFINITY;
+            float wmin = INFINITY, parts = 0.0f;
 #pragma unroll
-            for (int i = 0; i < kFpTile; ++i) {
-                float au, av, s;
-                int iu, iv;
-                voxel(i, cu0, cu1, cv0, cv1, au, av, iu, iv, s);
-                // in units of 1/S (exact: S is a power of two), rounded to the
-                // nearest integer, ties up (the same error bound as any
-                // round-to-nearest)
-                s *= S;
-                const float b = s * av;
-                const float a = s - b;
-                const float tr = a * au, br = b * au;
-                int* t0 = tile + (mad_i24(iv, TW, iu) + base);
-                int* t1 = t0 + TW;
-                atomicAdd(t0, cvt_nearest(a - tr));
-                atomicAdd(t0 + 1, cvt_nearest(tr));
-                atomicAdd(t1, cvt_nearest(b - br));
-                atomicAdd(t1 + 1, cvt_nearest(br));
+            for (int b = 0; b < 4; ++b) {
+                const float4 q0 = *(const float4*)bnds[b][jj];
+                const float4 q1 = *(const float4*)(bnds[b][jj] + 4);
+                umin = fminf(umin, q0.x);
+                umax = fmaxf(umax, q0.y);
+                vmin = fminf(vmin, q0.z);
+                vmx = fmaxf(vmx, q0.w);
+                wmin = fminf(wmin, q1.x);
+                parts += q1.y;
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < kFpTile; ++i) {
-                float au, av, s;
-                int iu, iv;
-                voxel(i, A.lo_u, A.hi_u, A.lo_v, A.hi_v, au, av, iu, iv, s);
-                const float b = s * av;
-                const float a = s - b;
-                const float tr = a * au, br = b * au;
-                const uint32_t off = (uint32_t)mad_i24(iv, Wp, iu) * 4u + centre_bytes;
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(a - tr, rsrc, off, 0, 0);
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(tr, rsrc, off + 4u, 0, 0);
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(b - br, rsrc, off, row_bytes, 0);
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(br, rsrc, off + 4u, row_bytes, 0);
+            if (uniform_f(parts) == 0.0f) continue;  // every box misses the detector
+            // the tile's extent (tap indices, clamped to the padded plane)
+            // and scale; bounds that are not finite take the 64-bit path
+            const bool finite = uniform_f(umax - umin) < 65536.0f &&
+                                uniform_f(vmx - vmin) < 65536.0f && uniform_f(wmin) > 0.0f;
+            const int U0 = finite ? max((int)floorf(uniform_f(umin)) - 1, A.lo_iu) : 0;
+            const int U1 = finite ? min((int)floorf(uniform_f(umax)) + 2, A.hi_iu + 1) : 0;
+            const int V0 = finite ? max((int)floorf(uniform_f(vmin)) - 1, A.lo_iv) : 0;
+            const int V1 = finite ? min((int)floorf(uniform_f(vmx)) + 2, A.hi_iv + 1) : 0;
+            const int TW = U1 - U0 + 1, TH = V1 - V0 + 1;
+            const float rmax = 1.0f / uniform_f(wmin);
+            const float bound = 4096.0f * vmax * rmax * rmax;
+            const bool use_lds = finite && TW * TH <= A.fp_tile && bound >= 1e-20f &&
+                                 bound <= 1e30f;
+            const int kt =
+                min(max((int)floorf(__builtin_log2f(2147483648.0f / bound)) - 1, -100), 100);
+            const float St = __builtin_ldexpf(1.0f, kt);
+            if (use_lds) {
+                for (int e = threadIdx.x; e < TW * TH; e += 256) tile[e] = 0;
+                __syncthreads();
             }
-        }
-        if (use_lds) {
-            __syncthreads();
-            for (int rr = wave; rr < TH; rr += 4) {
-                const uint32_t row_off =
-                    (uint32_t)mad_i24(V0 + rr, Wp, U0) * 4u + centre_bytes;
-                for (int cc = lane; cc < TW; cc += 64) {
-                    const float t = (float)tile[rr * TW + cc] * invS;
-                    if (t != 0.0f)
-                        __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(t, rsrc, row_off + 4u * cc,
-                                                                        0, 0);
+            const const_float* m = mats + 12 * (j0 + jj);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                // a box whose every tap is off the detector scatters nothing
+                // (the backprojection skips it: its taps read zeros)
+                if (bnds[box[h]][jj][5] == 0.0f) continue;
+                const float* row = rows[box[h]][jj];
+                const float4 r0 = *(const float4*)row;
+                const float4 r1 = *(const float4*)(row + 4);
+                const float4 r2 = *(const float4*)(row + 8);
+                const int au = __builtin_bit_cast(int, r2.y), av = __builtin_bit_cast(int, r2.z);
+                const float su2 = r1.y, sv2 = r2.x, sw2 = m[10];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    // (u' - a_u, v' - a_v, r) of voxel 8h + k of the line, as
+                    // the backprojection computes them
+                    float bu, bv, bw, u, v, r;
+                    column_base(r0.x, r0.y, r0.z, r0.w, r1.x, r1.z, r1.w, m[8], m[9], d_t[h],
+                                (float)k - h_r[h], bu, bv, bw);
+                    voxel_coords<kDivRcp, false>(bu, bv, bw, su2, sv2, sw2, (float)zz, u, v, r);
+                    const float fu = __builtin_amdgcn_fractf(u);
+                    const float fv = __builtin_amdgcn_fractf(v);
+                    const float s = val[8 * h + k] * (r * r);
+                    if (use_lds) {
+                        // tap (iu, iv) at tile index (iv - V0) TW + (iu - U0).
+                        // Clamping iu to [U0, U1 - 1] and iv to [V0, V1 - 1]
+                        // keeps all four taps inside the tile; it changes no
+                        // tap: the boxes project inside [umin, umax] x [vmin,
+                        // vmax], one pixel inside the tile, except where U0 =
+                        // lo_iu or U1 = hi_iu + 1 (likewise v), and there it is
+                        // the clamp to the padded plane's border that the
+                        // backprojection applies.
+                        const int ju = med3_i32(cvt_floor(u), U0 - au, U1 - 1 - au);
+                        const int jv = med3_i32(cvt_floor(v), V0 - av, V1 - 1 - av);
+                        int* t0p = tile + (mad_i24_ub(jv, TW, ju) + (av - V0) * TW + (au - U0));
+                        int* t1p = t0p + TW;
+                        // in units of 1/St (exact: St is a power of two),
+                        // rounded to the nearest integer, ties up
+                        const float sS = s * St;
+                        const float b = sS * fv;
+                        const float a = sS - b;
+                        const float tr = a * fu, br = b * fu;
+                        atomicAdd(t0p, cvt_nearest(a - tr));
+                        atomicAdd(t0p + 1, cvt_nearest(tr));
+                        atomicAdd(t1p, cvt_nearest(b - br));
+                        atomicAdd(t1p + 1, cvt_nearest(br));
+                    } else {
+                        const int ju = med3_i32(cvt_floor(u), A.lo_iu - au, A.hi_iu - au);
+                        const int jv = med3_i32(cvt_floor(v), A.lo_iv - av, A.hi_iv - av);
+                        const uint32_t off =
+                            (uint32_t)(mad_i24_ub(jv, Wp, ju) + av * Wp + au + A.origin_off);
+                        scatter_taps64(pl, off, Wp, s * Sg, fu, fv);
+                    }
                 }
             }
-            __syncthreads();
+            if (use_lds) {
+                __syncthreads();
+                for (int rr = wave; rr < TH; rr += 4) {
+                    unsigned long long* prow = pl + (V0 + rr) * Wp + U0 + A.origin_off;
+                    for (int cc = lane; cc < TW; cc += 64) {
+                        const int t = tile[rr * TW + cc];
+                        if (t != 0) atomicAdd(prow + cc, rescale_fixed(t, kt, kg));
+                    }
+                }
+                __syncthreads();
+            }
         }
+        __syncthreads();  // every thread has read the chunk's rows
     }
 }
 
@@ -367,13 +465,24 @@ hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// The interior of the planes (64-bit fixed point in units of 2^-kg, or
+// float) added to the caller's FP32 views.
 __global__ __launch_bounds__(256) void unstage_add_kernel(UnstageArgs a)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     const int k = blockIdx.y;
     const int view = blockIdx.z;
     if (j >= a.W) return;
-    const float v = a.planes[((size_t)view * a.Hp + k + kPad) * a.Wp + j + kPad];
+    // a plane holds Hp*Wp 64-bit sums, or Hp*Wp floats at its start
+    const unsigned long long* pl = a.planes + (size_t)view * a.Hp * a.Wp;
+    const size_t e = (size_t)(k + kPad) * a.Wp + j + kPad;
+    float v;
+    if (a.fixed) {
+        const int kg = fp_global_exponent(a.N, __uint_as_float(*a.vmax), a.rmax2);
+        v = __builtin_ldexpf((float)(long long)pl[e], -kg);
+    } else {
+        v = ((const float*)pl)[e];
+    }
     a.dst[((size_t)view * a.H + k) * a.W + j] += v;
 }
 

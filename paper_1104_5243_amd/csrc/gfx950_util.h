@@ -23,6 +23,24 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+// The median of x, lo and hi (x clamped to [lo, hi] when lo <= hi) in one
+// instruction.
+__device__ __forceinline__ int med3_i32(int x, int lo, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+// mad_i24 with a wave-uniform b (read from a scalar register; b must be
+// the same in every lane).
+__device__ __forceinline__ int mad_i24_ub(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // Raw buffer loads: a 32-bit byte offset per lane, the plane base in a
 // buffer descriptor, and the second tap row reached through the scalar
 // offset.  An offset outside the descriptor's range would read 0 instead of

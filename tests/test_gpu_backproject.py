@@ -81,6 +81,47 @@ def test_fused_parity_128(torch_dev, fdk_mod, stack, ref128):
     assert np.max(np.abs(got - ref128)) <= 1e-3 * rms_ref
 
 
+@pytest.mark.parametrize("divide,limit", [("rcp", FP32_TOL), ("rcp_nr", FP32_TOL),
+                                          ("ieee", FP32_TOL), ("rcp12", 2e-2)])
+def test_divide_variants_parity_128(torch_dev, fdk_mod, stack, ref128, divide, limit):
+    """The reciprocal variants of part 1 (the paper's accuracy study,
+    Section 7.2): v_rcp_f32, rcp with one Newton step and IEEE divisions
+    meet the FP32 target; the 12-bit reciprocal (the paper's rcpps
+    precision) is far less accurate, as the paper reports."""
+    torch, dev = torch_dev
+    geom, proj, proj_d = stack
+    vs, o = synth.volume_frame(128)
+    old = fdk_mod.set_divide(None)
+    try:
+        fdk_mod.set_divide(divide)
+        got = _gpu_bp(fdk_mod, torch, dev, proj_d, geom.P, 128, vs, o).cpu().numpy()
+    finally:
+        fdk_mod.set_divide(old)
+    err = oracle.rel_rmse(got, ref128)
+    print(f"divide {divide} 128^3: relRMSE {err:.3e}  PSNR {oracle.psnr(got, ref128):.1f} dB",
+          flush=True)
+    assert err <= limit
+    if divide == "rcp12":
+        assert err > FP32_TOL  # the truncated reciprocal is visibly worse
+
+
+def test_divide_variant_needs_the_default_layout(torch_dev, fdk_mod, stack):
+    torch, dev = torch_dev
+    geom, proj, proj_d = stack
+    vs, o = synth.volume_frame(16)
+    old_l, old_d = fdk_mod.set_layout(None), fdk_mod.set_divide(None)
+    try:
+        fdk_mod.set_layout("quads")
+        fdk_mod.set_divide("ieee")
+        vol = torch.zeros(16, 16, 16, device=dev)
+        with pytest.raises(fdk_mod.FdkError) as ei:
+            fdk_mod.backproject(vol, proj_d[:4], geom.P[:4], vs, o)
+        assert ei.value.code == fdk_mod.FDK_ERR_UNSUPPORTED
+    finally:
+        fdk_mod.set_layout(old_l)
+        fdk_mod.set_divide(old_d)
+
+
 def test_plain_parity_128(torch_dev, fdk_mod, stack, ref128):
     torch, dev = torch_dev
     geom, proj, proj_d = stack
@@ -89,8 +130,9 @@ def test_plain_parity_128(torch_dev, fdk_mod, stack, ref128):
     err = oracle.rel_rmse(got, ref128)
     print(f"plain 128^3: relRMSE {err:.3e}  PSNR {oracle.psnr(got, ref128):.1f} dB", flush=True)
     # the plain path rounds the world-coordinate matrices to FP32 and works in
-    # uncentred coordinates; it is the comparison baseline, held to 1e-4
-    assert err <= 1e-4
+    # uncentred coordinates (the comparison baseline); at 128^3 it still
+    # meets the FP32 target
+    assert err <= FP32_TOL
 
 
 def test_fused_is_deterministic(torch_dev, fdk_mod, stack):
@@ -276,31 +318,53 @@ def test_constant_image_on_gpu(torch_dev, fdk_mod, stack):
     assert oracle.rel_rmse(got, ref) <= 1e-6
 
 
+# 24^3 blocks of the 512^3 volume (x0, y0, z0), each with a reference of
+# its own size checked below: the centre, the rim of the field of view
+# (|x| or |y| near 120 mm), the cone's vertical edge off the axis (|z| near
+# 85-100 mm, where only some views reach a voxel) and inner blocks.
+BLOCKS_512 = [(244, 244, 244), (4, 244, 244), (244, 484, 244), (60, 60, 244), (20, 244, 70),
+              (400, 100, 300), (100, 100, 440), (100, 380, 60)]
+
+
 def test_fused_parity_512_sampled(torch_dev, fdk_mod, stack):
     """512^3 in the benchmark's launch configuration; the oracle checks
-    eight 24^3 blocks: the centre, corners (partly off the detector) and
-    faces."""
+    eight 24^3 blocks (BLOCKS_512), each held to the FP32 target on its own
+    relative RMSE."""
     torch, dev = torch_dev
     geom, proj, proj_d = stack
     N = 512
     vs, o = synth.volume_frame(N)
     vol = _gpu_bp(fdk_mod, torch, dev, proj_d, geom.P, N, vs, o)
     b = 24
-    starts = [(244, 244, 244), (0, 0, 0), (N - b, N - b, N - b), (0, N - b, 244),
-              (244, 0, N - b), (N - b, 244, 0), (100, 400, 60), (400, 100, 450)]
-    refs, gots = [], []
-    for (x0, y0, z0) in starts:
-        refs.append(oracle.backproject(proj, geom.P, N, vs, o, box=((x0, b), (y0, b), (z0, b))))
-        gots.append(vol[z0:z0 + b, y0:y0 + b, x0:x0 + b].cpu().numpy().astype(np.float64))
-    R = np.concatenate([r.ravel() for r in refs])
-    G = np.concatenate([g.ravel() for g in gots])
-    err = oracle.rel_rmse(G, R)
-    rms = float(np.sqrt(np.mean(R ** 2)))
-    for (x0, y0, z0), r, g in zip(starts, refs, gots):
-        e = float(np.sqrt(np.mean((g - r) ** 2)))
-        print(f"  block {(x0, y0, z0)}: rms err / rms(sample) {e / rms:.3e}", flush=True)
-        # a block of small values (edge of the field of view) is held to the
-        # sample's scale, not its own
-        assert e <= 3 * FP32_TOL * rms
-    print(f"fused 512^3 sampled: relRMSE {err:.3e}", flush=True)
+    worst = 0.0
+    for (x0, y0, z0) in BLOCKS_512:
+        ref = oracle.backproject(proj, geom.P, N, vs, o, box=((x0, b), (y0, b), (z0, b)))
+        got = vol[z0:z0 + b, y0:y0 + b, x0:x0 + b].cpu().numpy().astype(np.float64)
+        rms = float(np.sqrt(np.mean(ref ** 2)))
+        e = oracle.rel_rmse(got, ref)
+        worst = max(worst, e)
+        print(f"  block {(x0, y0, z0)}: rms(ref) {rms:.3e}, zeros {np.mean(ref == 0):.2f}, "
+              f"relRMSE {e:.3e}", flush=True)
+        # the block is not trivial: the voxels it checks received values
+        assert rms > 1e-5 and np.mean(ref == 0) < 0.6
+        assert e <= FP32_TOL
+    print(f"fused 512^3 sampled: worst block relRMSE {worst:.3e}", flush=True)
+
+
+def test_fused_parity_512_central_slab(torch_dev, fdk_mod, stack):
+    """The 512 x 512 x 128 central slab of the 512^3 workload (the sample
+    the benchmark reports), whole, against the oracle."""
+    torch, dev = torch_dev
+    geom, proj, proj_d = stack
+    N, S = 512, 128
+    vs, o = synth.volume_frame(N)
+    vol = _gpu_bp(fdk_mod, torch, dev, proj_d, geom.P, N, vs, o)
+    z0 = N // 2 - S // 2
+    got = vol[z0:z0 + S].cpu().numpy().astype(np.float64)
+    del vol
+    print(f"\n[oracle] 512x512x{S} slab", flush=True)
+    ref = oracle.backproject(proj, geom.P, N, vs, o, box=((0, N), (0, N), (z0, S)))
+    err = oracle.rel_rmse(got, ref)
+    print(f"fused 512^3 central slab: relRMSE {err:.3e}, PSNR {oracle.psnr(got, ref):.1f} dB",
+          flush=True)
     assert err <= FP32_TOL

@@ -76,11 +76,66 @@ def test_fp16_sign_and_range_handling(env):
     assert oracle.rel_rmse(vol.cpu().numpy(), ref) <= 1e-3
 
 
+def _reference_storage(torch, proj, dtype):
+    """Reduced-precision storage with plain torch arithmetic (the test's
+    reference): per-view k = floor(log4(2^14 / max|view|)) from the exact
+    binary exponent, clipped to [-60, 60], 0 for a zero view; values times
+    4^k rounded to nearest even."""
+    import math
+    if dtype == torch.bfloat16:
+        return proj.to(torch.bfloat16), None
+    amax = proj.abs().amax(dim=(1, 2)).double().cpu().numpy()
+    k = np.zeros(len(amax))
+    for i, a in enumerate(amax):
+        if a > 0:
+            m, e = math.frexp(a)  # a = m 2^e, m in [0.5, 1)
+            t = 14 - (e - 1) - (1 if m > 0.5 else 0)
+            k[i] = min(max(t // 2, -60), 60)
+    up = torch.from_numpy(4.0 ** k).to(device=proj.device, dtype=torch.float32)
+    return (proj * up[:, None, None]).to(torch.float16), (4.0 ** -k).astype(np.float32)
+
+
+@pytest.mark.parametrize("dtype_name", ["float16", "bfloat16"])
+def test_conversion_kernel_is_bit_identical_to_reference(env, dtype_name):
+    """fdk_convert_storage against the torch reference, on the filtered
+    stack plus views of extreme and boundary magnitudes (zero, exact powers
+    of two, subnormal-range, huge, negative)."""
+    torch, fdk, dev, geom, proj, proj_d = env
+    dtype = getattr(torch, dtype_name)
+    extra = proj_d[:8].clone()
+    extra[0] = 0.0
+    extra[1] *= 2.0 ** 14 / extra[1].abs().amax()           # amax exactly 2^14
+    extra[2] *= 2.0 ** 13 / extra[2].abs().amax()           # amax exactly 2^13
+    extra[3] *= 1e-30 / extra[3].abs().amax()
+    extra[4] *= 3e30 / extra[4].abs().amax()
+    extra[5] = -extra[5]
+    extra[6, 100, 200] = -7.25                              # a single dominant value
+    extra[7] *= 1e-41 / extra[7].abs().amax()               # FP32 subnormal range
+    stack = torch.cat([proj_d, extra])
+    got, gs = fdk.to_storage(stack, dtype)
+    ref, rs = _reference_storage(torch, stack, dtype)
+    torch.cuda.synchronize()
+    assert got.dtype == dtype and got.shape == stack.shape
+    assert torch.equal(got.view(torch.int16), ref.view(torch.int16))
+    if dtype == torch.float16:
+        np.testing.assert_array_equal(gs, rs)
+        # the scaled magnitudes land in (2^12, 2^14] where k is not clipped
+        amax = stack.abs().amax(dim=(1, 2)).double().cpu().numpy()
+        scaled = amax / gs
+        k = (1 - np.frexp(gs.astype(np.float64))[1]) // 2  # gs = 4^-k exactly
+        ok = (amax > 0) & (np.abs(k) < 60)
+        assert np.all((scaled[ok] > 2.0 ** 12) & (scaled[ok] <= 2.0 ** 14))
+    else:
+        assert gs is None
+
+
 @pytest.mark.parametrize("dtype_name", ["float32", "float16", "bfloat16"])
 def test_1024_sub_blocks(env, dtype_name):
     """1024^3 (4 GiB accumulator, 64-bit addressing) with FP32, FP16 or
-    BF16 storage; the oracle checks the centre block [448,576)^3 and an
-    edge block [64,192) x [448,576) x [64,192) (x, y, z)."""
+    BF16 storage; the oracle checks the centre block [448,576)^3 (which
+    straddles the 2 GiB byte offset of the volume) and an edge block
+    [64,192) x [448,576) x [64,192) (x, y, z) where the cone leaves the
+    detector vertically, each against the target of its storage type."""
     torch, fdk, dev, geom, proj, proj_d = env
     N = 1024
     vs, o = synth.volume_frame(N)
@@ -90,19 +145,17 @@ def test_1024_sub_blocks(env, dtype_name):
     fdk.backproject(vol, stack, geom.P, vs, o, view_scale=scale)
     torch.cuda.synchronize()
     blocks = [((448, 128), (448, 128), (448, 128)), ((64, 128), (448, 128), (64, 128))]
-    num = den = 0.0
+    limit = 1e-5 if dtype_name == "float32" else 1e-3
     for box in blocks:
         (x0, nx), (y0, ny), (z0, nz) = box
         ref = _ref_1024(proj, geom, box)
         got = vol[z0:z0 + nz, y0:y0 + ny, x0:x0 + nx].double().cpu().numpy()
         e = oracle.rel_rmse(got, ref)
-        print(f"  {dtype_name} 1024^3 block {box}: relRMSE {e:.3e}", flush=True)
-        num += float(np.sum((got - ref) ** 2))
-        den += float(np.sum(ref ** 2))
-    err = (num / den) ** 0.5
-    print(f"{dtype_name} 1024^3 sub-blocks: relRMSE {err:.3e}", flush=True)
-    # the centre block straddles the 2 GiB byte offset of the 4 GiB volume
-    assert err <= (1e-5 if dtype_name == "float32" else 1e-3)
+        print(f"  {dtype_name} 1024^3 block {box}: rms(ref) {np.sqrt(np.mean(ref ** 2)):.3e}, "
+              f"relRMSE {e:.3e}", flush=True)
+        # each block on its own (the edge block's values are ~50x smaller
+        # than the centre's; a pooled figure would be the centre's)
+        assert e <= limit
     del vol
 
 
