@@ -42,8 +42,8 @@ PAPER_GUPS = 3.79
 # the sources the fused kernel's launches depend on (kernel, argument
 # structs, device helpers, host set-up with its default layout)
 KERNEL_SRC = [os.path.join(ROOT, "paper_1104_5243_amd", "csrc", f)
-              for f in ("bp_kernels.hip", "gfx950_util.h", "fdk_internal.h", "api_internal.h",
-                        "api.hip")]
+              for f in ("bp_kernels.hip", "anchor.h", "gfx950_util.h", "fdk_internal.h",
+                        "api_internal.h", "api.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bp_fused_fdk512_traffic.txt")
 
 
@@ -85,6 +85,32 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def clipped_fraction(geom, N, vs, origin, stride=8):
+    """Fraction of (voxel, view) pairs with every tap off the detector
+    (u <= -1, u >= W, v <= -1 or v >= H, or w <= 0), over a sub-grid of
+    voxels (every `stride`-th per axis) and all views, in FP64."""
+    import numpy as np
+    idx = np.arange(0, N, stride, dtype=np.float64)
+    X = origin[0] + vs * idx
+    Y = origin[1] + vs * idx
+    Z = origin[2] + vs * idx
+    xx, yy = np.meshgrid(X, Y, indexing="ij")
+    off = 0
+    total = 0
+    for P in geom.P:
+        for z in Z:
+            uw = P[0, 0] * xx + P[0, 1] * yy + P[0, 2] * z + P[0, 3]
+            vw = P[1, 0] * xx + P[1, 1] * yy + P[1, 2] * z + P[1, 3]
+            w = P[2, 0] * xx + P[2, 1] * yy + P[2, 2] * z + P[2, 3]
+            u = uw / w
+            v = vw / w
+            miss = (w <= 0) | (u <= -1) | (u >= geom.W) | (v <= -1) | (v >= geom.H)
+            off += int(miss.sum())
+            total += miss.size
+    return {"exact_fraction": round(off / total, 4),
+            "sample": f"every {stride}th voxel per axis x all {geom.n_views} views, FP64"}
 
 
 def _timed(torch, fdk, fn, warmup, steps):
@@ -553,6 +579,32 @@ def main() -> int:
         }
         log(f"oracle: {tc:.1f}s, relRMSE {out['rel_rmse_vs_oracle']:.3e}")
         out["cpu_baseline"]["cpu_model"] = cpu_model()
+
+        # the divide variants of part 1 (the paper's accuracy study, Section
+        # 7.2) on the same stack: throughput and error on the same slab
+        divides = {}
+        for dv in ("rcp", "rcp_nr", "ieee", "rcp12"):
+            fdk.set_divide(dv)
+            step("fused")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                step("fused")
+            torch.cuda.synchronize()
+            td = (time.perf_counter() - t0) / 3
+            gd = vol[z0:z0 + S].double().cpu().numpy()
+            divides[dv] = {"value": round(updates / td / 1e9, 2), "unit": "GUP/s",
+                           "ms_per_step": round(td * 1e3, 3),
+                           "rel_rmse_vs_oracle": float(f"{oracle.rel_rmse(gd, ref):.3e}"),
+                           "psnr_db_vs_oracle": round(oracle.psnr(gd, ref), 1)}
+        fdk.set_divide("rcp")
+        out["divide_variants"] = divides
+        log(f"divide variants: {divides}")
+
+        # clipping: the exact fraction of (voxel, view) pairs whose four taps
+        # all lie off the detector (every 8th voxel per axis, all views)
+        out["clipping"] = clipped_fraction(geom, N, vs, origin)
+        log(f"clipping: {out['clipping']}")
 
         # reduced-precision storage of the same stack on the same GPU
         variants = {}

@@ -77,8 +77,8 @@ struct Anchor {
     float sw_t, sw_r, sw2;   // the w row
     int au, av;
     bool skip;               // every voxel of the box misses the detector
-    // the box's projection (u', v' including the anchor; valid when the
-    // lower bound wmin of w over the box is > 0)
+    // the hull of the box's projection (u', v' including the anchor) and the
+    // smallest w over the box; valid when wmin > 0
     float umin, umax, vmin, vmax, wmin;
 };
 
@@ -131,31 +131,39 @@ __device__ __forceinline__ Anchor make_anchor(const FusedArgs& A, int view, cons
     a.sw_t = yf ? sw0 : sw1;
     a.sw_r = yf ? sw1 : sw0;
     a.sw2 = (float)S[10];
-    // Clipping (Section 3.3): with w > 0 on the box, u' - a_u lies between
-    // the extremes of (nu +- Ru) / (nw -+ Rw), nu and nw the numerator and
-    // w at the box centre, Ru and Rw their largest changes over the box; if
-    // the whole interval falls off the detector (0.5 pixel margins), every
-    // tap of every voxel of the box is zero.
+    // Clipping (Section 3.3).  With w > 0 on the box (w is affine: its
+    // minimum is at a corner), the box projects inside the convex hull of
+    // its 8 corners' projections; if that hull falls off the detector (0.5
+    // pixel margins), every tap of every voxel of the box is zero and the
+    // box skips the view.  Corners from the anchored FP32 values (their
+    // rounding is far below the margins).
     bool skip = !valid;
     a.umin = a.vmin = -INFINITY;
     a.umax = a.vmax = INFINITY;
     a.wmin = 0.0f;
     if (ANCHOR && valid) {
-        const float nu = (float)fma(S[2], cz, fma(S[1], cy, fma(S[0], cx, S[3])));
-        const float nv = (float)fma(S[6], cz, fma(S[5], cy, fma(S[4], cx, S[7])));
-        const float nw = (float)fma(S[10], cz, fma(S[9], cy, fma(S[8], cx, S[11])));
-        const float ru = fabsf(su0) * f.hx + fabsf(su1) * f.hy + fabsf(a.su2) * f.hz;
-        const float rv = fabsf(sv0) * f.hx + fabsf(sv1) * f.hy + fabsf(a.sv2) * f.hz;
-        const float rw = fabsf(sw0) * f.hx + fabsf(sw1) * f.hy + fabsf(a.sw2) * f.hz;
-        const float d0 = nw - rw, d1 = nw + rw;
-        if (d0 > 0.0f) {
-            const float i0 = 1.0f / d0, i1 = 1.0f / d1;
-            const float u1 = nu + ru, u0 = nu - ru, v1 = nv + rv, v0 = nv - rv;
-            a.umax = fmaxf(u1 * i0, u1 * i1) + (float)au;
-            a.umin = fminf(u0 * i0, u0 * i1) + (float)au;
-            a.vmax = fmaxf(v1 * i0, v1 * i1) + (float)av;
-            a.vmin = fminf(v0 * i0, v0 * i1) + (float)av;
-            a.wmin = d0;
+        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        float wmin = INFINITY;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float ex = (k & 1) ? f.hx : -f.hx, ey = (k & 2) ? f.hy : -f.hy;
+            const float ez = (k & 4) ? 2.0f * f.hz : 0.0f;
+            const float nu = fmaf(ez, (float)S[2], fmaf(ey, su1, fmaf(ex, su0, a.uc)));
+            const float nv = fmaf(ez, (float)S[6], fmaf(ey, sv1, fmaf(ex, sv0, a.vc)));
+            const float nw = fmaf(ez, (float)S[10], fmaf(ey, sw1, fmaf(ex, sw0, a.wc)));
+            const float r = __builtin_amdgcn_rcpf(nw);  // (~1 ulp: far inside the margins)
+            umin = fminf(umin, nu * r);
+            umax = fmaxf(umax, nu * r);
+            vmin = fminf(vmin, nv * r);
+            vmax = fmaxf(vmax, nv * r);
+            wmin = fminf(wmin, nw);
+        }
+        if (wmin > 0.0f) {
+            a.umin = umin + (float)au;
+            a.umax = umax + (float)au;
+            a.vmin = vmin + (float)av;
+            a.vmax = vmax + (float)av;
+            a.wmin = wmin;
             skip = a.umax < A.skip_lo_u || a.umin > A.skip_hi_u || a.vmax < A.skip_lo_v ||
                    a.vmin > A.skip_hi_v;
         }

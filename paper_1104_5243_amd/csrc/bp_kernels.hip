@@ -353,6 +353,8 @@ __device__ __forceinline__ float bilerp16(TBF16, uint2 q, float au, float av)
 #endif
 constexpr int kGroup = FDK_GROUP;
 static_assert(kWaveX * kWaveY == 64, "a wave covers 64 columns");
+static_assert(fused_z(kF32) % kGroup == 0 && fused_z(kF16) % kGroup == 0,
+              "a thread's z voxels split into whole groups");
 
 // One view's contribution to the fused_z voxels of this thread, from the
 // view's anchor (uniform over the wave) and the thread's offsets (d_t, d_r)
@@ -362,7 +364,7 @@ static_assert(kWaveX * kWaveY == 64, "a wave covers 64 columns");
 // outside the plane gives a byte offset outside the buffer's range, which
 // reads as zero (the host has bounded the rows so that the offset cannot
 // wrap into the plane).
-template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV>
+template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV, bool CLAMP = true>
 __device__ __forceinline__ void accumulate_view(
     const FusedArgs& A, float uc, float vc, float wc, float su_t, float su_r, float su2,
     float sv_t, float sv_r, float sv2, float sw_t, float sw_r, float sw2, int lo_u, int hi_u,
@@ -391,8 +393,8 @@ __device__ __forceinline__ void accumulate_view(
             // part 2
             au[q] = __builtin_amdgcn_fractf(u);
             av[q] = __builtin_amdgcn_fractf(v);
-            const int ju = med3_i32(cvt_floor(u), lo_u, hi_u);
-            const int jv = VCLAMP ? med3_i32(cvt_floor(v), lo_v, hi_v) : cvt_floor(v);
+            const int ju = CLAMP ? med3_i32(cvt_floor(u), lo_u, hi_u) : cvt_floor(u);
+            const int jv = CLAMP && VCLAMP ? med3_i32(cvt_floor(v), lo_v, hi_v) : cvt_floor(v);
             const uint32_t off = (uint32_t)(mad_i24_ub(jv, Wp, ju) + base) * kElem;
             if constexpr (kIsF32)
                 load_taps<LAYOUT>(TT{}, rsrc, off, row_bytes, tl[q], tr[q], bl[q], br[q]);
@@ -422,6 +424,12 @@ __device__ __forceinline__ void accumulate_view(
         }
     }
 }
+
+// a second copy of the view's voxel loop without tap clamps, taken by the
+// views whose every tap index of the box lies inside the clamp range
+#ifndef FDK_INSIDE
+#define FDK_INSIDE 0
+#endif
 
 // waves per SIMD the register budget is fitted to (512 VGPRs / 8 = 64)
 #ifndef FDK_MIN_WAVES
@@ -485,9 +493,9 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     // view at a wave-uniform address (a broadcast), so that they occupy
     // vector registers only while their view is processed.  Row: uc, vc,
     // wc, the u and v slopes (transverse, ray, z), the element offset of
-    // pixel (a_u + ku, a_v + kv) in a plane, and the tap index clamp ranges
-    // shifted by the anchor.  (The w row is the folded matrix's, read as
-    // scalars.)
+    // pixel (a_u + ku, a_v + kv) in a plane, the tap index clamp ranges
+    // shifted by the anchor, and the w row's z slope.  (Its x and y slopes
+    // are the folded matrix's, read as scalars.)
     __shared__ float anchors[kWgWaves][64][16];
     float(*an_rows)[16] = anchors[wave];
     const uint32_t plane_bytes = (uint32_t)(A.plane * (long long)kElem);
@@ -496,10 +504,15 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     for (int j0 = 0; j0 < A.count; j0 += 64) {
         // lane L: the anchor of view j0 + L; WCHECK batches (some voxel may
         // have w <= 0) keep a_u = a_v = 0 and skip nothing
-        uint64_t skip;
+        uint64_t skip, inside;
         {
             const Anchor an = make_anchor<!WCHECK>(A, j0 + lane, bf);
             skip = __ballot(an.skip);
+            // every tap index of the box within the clamp range already
+            // (half a pixel of margin): the view needs no clamps
+            inside = __ballot(!WCHECK && an.wmin > 0.0f &&
+                              an.umin >= (float)A.lo_iu + 0.5f && an.umax <= (float)A.hi_iu + 0.5f &&
+                              an.vmin >= (float)A.lo_iv + 0.5f && an.vmax <= (float)A.hi_iv + 0.5f);
             const int base = an.av * A.Wp + an.au + A.origin_off;
             float* row = an_rows[lane];
             *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
@@ -507,7 +520,9 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
             *(float4*)(row + 8) = make_float4(an.sv2, __builtin_bit_cast(float, base),
                                               __builtin_bit_cast(float, A.lo_iu - an.au),
                                               __builtin_bit_cast(float, A.hi_iu - an.au));
-            *(int4*)(row + 12) = make_int4(A.lo_iv - an.av, A.hi_iv - an.av, 0, 0);
+            *(float4*)(row + 12) =
+                make_float4(__builtin_bit_cast(float, A.lo_iv - an.av),
+                            __builtin_bit_cast(float, A.hi_iv - an.av), an.sw2, 0.0f);
         }
         __syncthreads();
         const int jn = min(64, A.count - j0);
@@ -518,11 +533,22 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
             const float4 r0 = *(const float4*)an_rows[jj];
             const float4 r1 = *(const float4*)(an_rows[jj] + 4);
             const int4 r2 = *(const int4*)(an_rows[jj] + 8);
-            const int2 r3 = *(const int2*)(an_rows[jj] + 12);
+            const float4 r3 = *(const float4*)(an_rows[jj] + 12);
             const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
+            // (the w row's z slope from LDS, a vector register: the slice
+            // FMAs take their slice index as an inline literal)
+#if FDK_INSIDE
+            if ((inside >> jj) & 1)
+                accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV, false>(
+                    A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                    __builtin_bit_cast(float, r2.x), m[8], m[9], r3.z, 0, 0, 0, 0, r2.y, d_t, d_r,
+                    rsrc, acc);
+            else
+#endif
             accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV>(
                 A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, __builtin_bit_cast(float, r2.x),
-                m[8], m[9], m[10], r2.z, r2.w, r3.x, r3.y, r2.y, d_t, d_r, rsrc, acc);
+                m[8], m[9], r3.z, r2.z, r2.w, __builtin_bit_cast(int, r3.x),
+                __builtin_bit_cast(int, r3.y), r2.y, d_t, d_r, rsrc, acc);
         }
         __syncthreads();  // every wave has read its rows before the next chunk's
     }

@@ -154,7 +154,9 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
                 make_float4(an.sv2, __builtin_bit_cast(float, an.av * Wp + an.au + A.origin_off),
                             __builtin_bit_cast(float, A.lo_iu - an.au),
                             __builtin_bit_cast(float, A.hi_iu - an.au));
-            *(int4*)(row + 12) = make_int4(A.lo_iv - an.av, A.hi_iv - an.av, 0, 0);
+            *(float4*)(row + 12) =
+                make_float4(__builtin_bit_cast(float, A.lo_iv - an.av),
+                            __builtin_bit_cast(float, A.hi_iv - an.av), an.sw2, 0.0f);
         }
         __syncthreads();
         const int jn = min(64, A.count - j0);
@@ -164,11 +166,12 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
             const float4 r0 = *(const float4*)an_rows[jj];
             const float4 r1 = *(const float4*)(an_rows[jj] + 4);
             const int4 r2 = *(const int4*)(an_rows[jj] + 8);
-            const int2 r3 = *(const int2*)(an_rows[jj] + 12);
+            const float4 r3f = *(const float4*)(an_rows[jj] + 12);
+            const int2 r3 = make_int2(__builtin_bit_cast(int, r3f.x), __builtin_bit_cast(int, r3f.y));
             float bu, bv, bw;
             column_base(r0.x, r0.y, r0.z, r0.w, r1.x, r1.z, r1.w, m[8], m[9], d_t, d_r, bu, bv,
                         bw);
-            const float su2 = r1.y, sv2 = __builtin_bit_cast(float, r2.x), sw2 = m[10];
+            const float su2 = r1.y, sv2 = __builtin_bit_cast(float, r2.x), sw2 = r3f.z;
 #pragma unroll
             for (int i = 0; i < kFpZ; ++i) {
                 float u, v, r;
@@ -334,7 +337,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
             *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
             *(float4*)(row + 4) = make_float4(an.su_r, an.su2, an.sv_t, an.sv_r);
             *(float4*)(row + 8) = make_float4(an.sv2, __builtin_bit_cast(float, an.au),
-                                              __builtin_bit_cast(float, an.av), 0.0f);
+                                              __builtin_bit_cast(float, an.av), an.sw2);
             // a skipped box takes no part in the footprint
             const bool part = !an.skip;
             *(float4*)bnds[b][jv] = make_float4(part ? an.umin : INFINITY,
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
                 const float4 r1 = *(const float4*)(row + 4);
                 const float4 r2 = *(const float4*)(row + 8);
                 const int au = __builtin_bit_cast(int, r2.y), av = __builtin_bit_cast(int, r2.z);
-                const float su2 = r1.y, sv2 = r2.x, sw2 = m[10];
+                const float su2 = r1.y, sv2 = r2.x, sw2 = r2.w;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     // (u' - a_u, v' - a_v, r) of voxel 8h + k of the line, as
