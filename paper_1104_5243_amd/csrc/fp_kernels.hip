@@ -307,6 +307,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     __syncthreads();
     vmax = fmaxf(fmaxf(wave_max[0], wave_max[1]), fmaxf(wave_max[2], wave_max[3]));
     if (vmax == 0.0f) return;  // nothing to project (uniform over the block)
+    for (int e = threadIdx.x; e < A.fp_tile; e += 256) tile[e] = 0;
 
     // the thread's two boxes along its line (b = bx + 2 by) and its offsets
     const int tb = tt >> 3;
@@ -382,10 +383,6 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
             const int kt =
                 min(max((int)floorf(__builtin_log2f(2147483648.0f / bound)) - 1, -100), 100);
             const float St = __builtin_ldexpf(1.0f, kt);
-            if (use_lds) {
-                for (int e = threadIdx.x; e < TW * TH; e += 256) tile[e] = 0;
-                __syncthreads();
-            }
             const const_float* m = mats + 12 * (j0 + jj);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -443,10 +440,13 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
             }
             if (use_lds) {
                 __syncthreads();
+                // each entry read and cleared: the tile is all zero again
+                // for the next view (it is zeroed once, before the first)
                 for (int rr = wave; rr < TH; rr += 4) {
                     unsigned long long* prow = pl + (V0 + rr) * Wp + U0 + A.origin_off;
                     for (int cc = lane; cc < TW; cc += 64) {
                         const int t = tile[rr * TW + cc];
+                        tile[rr * TW + cc] = 0;
                         if (t != 0) atomicAdd(prow + cc, rescale_fixed(t, kt, kg));
                     }
                 }
