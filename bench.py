@@ -288,13 +288,23 @@ def bench_prefilter(args, torch, fdk, synth, dev):
 
     t, kms, launches = _timed(torch, fdk, step, args.warmup, args.steps)
     rows = V * H
-    # FFT convolution of two rows per complex transform of length L (radix 4,
-    # 34 flop per butterfly; radix 2, 10 flop), forward and inverse, and the
-    # spectrum product (6 flop per point)
-    L, lg = 4, 2
-    while L < 2 * W - 1:
-        L, lg = 2 * L, lg + 1
-    per_transform = (lg // 2) * (L // 4) * 34 + (lg % 2) * (L // 2) * 10
+    # FFT convolution of two rows per complex transform of length L, forward
+    # and inverse, and the spectrum product (6 flop per point).  The library
+    # takes L = 2560 = 10 x 16 x 16 for 513 <= W <= 1280: per 10-point group
+    # two 5-point DFTs (48 flop each), 4 twiddle products and 10 complex
+    # additions (44) and 9 twiddle products (54), 194 flop; per 16-point
+    # group two radix-4 stages, 8 butterflies of 34 flop.  Power-of-two L:
+    # radix 4 (34 flop per butterfly) and one radix-2 stage (10 flop) if
+    # log2 L is odd.  (Counted without the pruning of zero inputs and unused
+    # outputs that the kernels apply.)
+    if 512 < W and 2 * W - 1 <= 2560:
+        L = 2560
+        per_transform = (L // 10) * 194 + 2 * (L // 16) * 8 * 34
+    else:
+        L, lg = 4, 2
+        while L < 2 * W - 1:
+            L, lg = 2 * L, lg + 1
+        per_transform = (lg // 2) * (L // 4) * 34 + (lg % 2) * (L // 2) * 10
     flop = (rows + 1) // 2 * (2 * per_transform + 6 * L)
     ks = kms / 1e3
     ach = flop * args.steps / ks / 1e12
@@ -314,9 +324,12 @@ def bench_prefilter(args, torch, fdk, synth, dev):
         f"fdk512 pre-filter: {V} line-integral views of {W}x{H}, FP32 in/out, FP64 inside",
         {"bound": "alu", "achieved": round(ach, 3), "peak": 78.6, "unit": "TFLOP/s",
          "frac": round(ach / 78.6, 4), "traffic": None,
-         "kernel": ("fft_conv4096_real_kernel (FP64 FFT, L=4096, radix-16 passes in "
+         "kernel": ("fft_conv2560_kernel<true> (FP64 FFT, L=2560 = 10x16x16, passes in "
+                    "registers, two rows per transform, real Ram-Lak spectrum)" if L == 2560 else
+                    "fft_conv4096_real_kernel (FP64 FFT, L=4096, radix-16 passes in "
                     "registers, two rows per transform, real Ram-Lak spectrum)" if L == 4096 else
                     f"fft_conv_kernel (FP64 FFT, L={L}, two rows per transform)"),
+         "flop_per_row_pair": 2 * per_transform + 6 * L,
          "launches_per_step": launches // args.steps,
          "kernel_ms_per_step": round(kms / args.steps, 3)},
         None if tc is None else

@@ -21,23 +21,26 @@ int run_fft_conv(FftConvArgs A, hipStream_t stream)
         L <<= 1;
         ++log2L;
     }
-    // rows of 513..1024 samples also take L = 4096: more zero padding leaves
-    // the linear convolution unchanged, and the register-resident L = 4096
-    // kernel convolves a row pair in about a third of the time the general
-    // kernel takes at L = 2048 (learned filter at 128^3: 1.0 -> 0.4 ms)
-    if (L == kFftMax / 2) {
-        L = kFftMax;
-        ++log2L;
+    // rows of 513..1280 samples take the mixed-radix L = 2560 kernel (more
+    // zero padding than 2W - 1 leaves the linear convolution unchanged):
+    // registers hold each pass, and the transform is 0.6 of L = 4096's;
+    // against the general kernel at L = 2048, the register-resident kernels
+    // convolve a row pair in about a third of the time (learned filter at
+    // 128^3: 1.0 -> 0.4 ms at L = 4096); longer rows take L = 4096
+    if (A.W > 512 && 2 * A.W - 1 <= kL2560) {
+        L = kL2560;
+        log2L = 0;
     }
     A.L = L;
     A.log2L = log2L;
     std::lock_guard<std::mutex> lock(g_stage_mu);
     Staging* st = nullptr;
     const size_t tables = A.weighted ? ((size_t)A.views + A.H) * A.W * sizeof(double) : 0;
-    int rc = acquire_staging((size_t)(kFftMax + L) * 16 + tables, stream, &st);
+    int rc = acquire_staging((size_t)(kFftMax + kL2560 + L) * 16 + tables, stream, &st);
     if (rc != FDK_OK) return rc;
     A.tw = (double2*)st->ptr;
-    A.spectrum = A.tw + kFftMax;
+    A.tw2560 = A.tw + kFftMax;
+    A.spectrum = A.tw2560 + kL2560;
     A.parker = (double*)(A.spectrum + L);
     A.cosw = A.parker + (size_t)A.views * A.W;
     hipEvent_t t0;

@@ -19,11 +19,12 @@
 // (the ramp removes each row's mean: its output is a small difference of
 // large terms), rounded once to FP32 on output.
 //
-// Two kernels run the convolution: a general one for any L (its passes go
-// through LDS, pairs of radix-4 stages at a time), and one for L = 4096 that
-// keeps each pass in registers and fuses the loads, the spectrum product and
-// the stores into the passes.  The host takes L = 4096 for rows of 513 to
-// 2048 samples (the Feldkamp pre-filter's 1248, the learned filter's 624).
+// Three kernels run the convolution: a general one for power-of-two L (its
+// passes go through LDS, pairs of radix-4 stages at a time), and two that
+// keep each pass in registers and fuse the loads, the spectrum product and
+// the stores into the passes: L = 2560 (mixed radix 10 x 16 x 16) for rows
+// of 513 to 1280 samples (the Feldkamp pre-filter's 1248, the learned
+// filter's 624), L = 4096 for rows of 1281 to 2048.
 #include "learn_internal.h"
 
 namespace fdk {
@@ -219,13 +220,19 @@ __device__ void fft_inverse(double2* x, int L, int log2L, const double2* tw)
     }
 }
 
-__global__ __launch_bounds__(256) void fft_twiddle_kernel(double2* tw)
+// exp(-2 pi i k / kFftMax) for k < kFftMax into tw and, if tw2560 is not
+// null, exp(-2 pi i k / 2560) for k < 2560 into tw2560
+__global__ __launch_bounds__(256) void fft_twiddle_kernel(double2* tw, double2* tw2560)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= kFftMax) return;
     double s, c;
     sincospi(2.0 * (double)k / (double)kFftMax, &s, &c);
     tw[k] = {c, -s};
+    if (tw2560 && k < kL2560) {
+        sincospi(2.0 * (double)k / (double)kL2560, &s, &c);
+        tw2560[k] = {c, -s};
+    }
 }
 
 __device__ __forceinline__ double ramlak_tap(int n, double tau)
@@ -236,24 +243,24 @@ __device__ __forceinline__ double ramlak_tap(int n, double tau)
     return 0.0;
 }
 
-// Spectrum of the taps, in the forward transform's order, times scale / L.
-// Taps h[n] for -(W-1) <= n <= W-1: the Ram-Lak kernel (taps == nullptr)
-// or h[n] = taps[pad - n] (transpose: taps[K - 1 - (pad - n)]).
+// Tap h[n] of the call, -(W-1) <= n <= W-1: the Ram-Lak kernel (taps ==
+// nullptr) or h[n] = taps[pad - n] (transpose: taps[K - 1 - (pad - n)]).
+__device__ __forceinline__ double conv_tap(const FftConvArgs& a, int n)
+{
+    if (!a.taps) return ramlak_tap(n < 0 ? -n : n, a.tau);
+    const int t = a.pad - n;
+    return (t >= 0 && t < a.K) ? (double)a.taps[a.transpose ? a.K - 1 - t : t] : 0.0;
+}
+
+// Spectrum of the taps, in the forward transform's order, times scale / L
+// (power-of-two L).
 __global__ __launch_bounds__(kFftThreads) void fft_spectrum_kernel(FftConvArgs a)
 {
     __shared__ double2 x[kFftLds];
     for (int p = threadIdx.x; p < a.L; p += kFftThreads) x[px(p)] = {0.0, 0.0};
     __syncthreads();
-    for (int n = -(a.W - 1) + (int)threadIdx.x; n <= a.W - 1; n += kFftThreads) {
-        double h;
-        if (!a.taps) {
-            h = ramlak_tap(n < 0 ? -n : n, a.tau);
-        } else {
-            const int t = a.pad - n;
-            h = (t >= 0 && t < a.K) ? (double)a.taps[a.transpose ? a.K - 1 - t : t] : 0.0;
-        }
-        x[px(n < 0 ? n + a.L : n)] = {h, 0.0};
-    }
+    for (int n = -(a.W - 1) + (int)threadIdx.x; n <= a.W - 1; n += kFftThreads)
+        x[px(n < 0 ? n + a.L : n)] = {conv_tap(a, n), 0.0};
     __syncthreads();
     fft_forward(x, a.L, a.log2L, a.tw);
     const double f = a.scale / (double)a.L;
@@ -545,14 +552,15 @@ __device__ __forceinline__ int posn(int t, int a, int b)
 }
 
 // Rows r0 and r0 + 1 (if two) of the call, with the Feldkamp weights when
-// a.weighted, into the first forward pass's registers (element
-// pos1(t, q, b) of the complex row r0 + i r1; zero from W on).  Branch-free,
-// with every lane's address clamped into the row and the weighting test
-// outside the element loop, so that all the loads are in flight together:
-// guarded per element, the compiler waited for each element's loads before
-// issuing the next ones (fdk512's pre-filter: 5.87 ms against 4.32 ms).
-__device__ __forceinline__ void load_rows4096(const FftConvArgs& a, int r0, bool two, int t,
-                                              double2 (&v)[4][4])
+// a.weighted: y[k] = element t + 256 k of the complex row r0 + i r1 (zero
+// from W on), k < NK.  Branch-free, with every lane's address clamped into
+// the row and the weighting test outside the element loop, so that all the
+// loads are in flight together: guarded per element, the compiler waited for
+// each element's loads before issuing the next ones (fdk512's pre-filter at
+// L = 4096: 5.87 ms against 4.32 ms).
+template <int NK>
+__device__ __forceinline__ void load_rows(const FftConvArgs& a, int r0, bool two, int t,
+                                          double2* y)
 {
     const int r1 = two ? r0 + 1 : r0;
     const int view0 = r0 / a.H, k0 = r0 - view0 * a.H;
@@ -565,26 +573,30 @@ __device__ __forceinline__ void load_rows4096(const FftConvArgs& a, int r0, bool
         const double* p0 = a.parker + (size_t)view0 * a.W;
         const double* p1 = a.parker + (size_t)view1 * a.W;
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int p = pos1(t, q, b);
-                const int pc = min(p, a.W - 1);
-                const double x0 = (double)in0[pc] * c0[pc] * p0[pc];
-                const double x1 = (double)in1[pc] * c1[pc] * p1[pc];
-                v[q][b] = p < a.W ? double2{x0, two ? x1 : 0.0} : double2{0.0, 0.0};
-            }
+        for (int k = 0; k < NK; ++k) {
+            const int p = t + 256 * k;
+            const int pc = min(p, a.W - 1);
+            const double x0 = (double)in0[pc] * c0[pc] * p0[pc];
+            const double x1 = (double)in1[pc] * c1[pc] * p1[pc];
+            y[k] = p < a.W ? double2{x0, two ? x1 : 0.0} : double2{0.0, 0.0};
+        }
     } else {
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int p = pos1(t, q, b);
-                const int pc = min(p, a.W - 1);
-                const double x0 = (double)in0[pc], x1 = (double)in1[pc];
-                v[q][b] = p < a.W ? double2{x0, two ? x1 : 0.0} : double2{0.0, 0.0};
-            }
+        for (int k = 0; k < NK; ++k) {
+            const int p = t + 256 * k;
+            const int pc = min(p, a.W - 1);
+            const double x0 = (double)in0[pc], x1 = (double)in1[pc];
+            y[k] = p < a.W ? double2{x0, two ? x1 : 0.0} : double2{0.0, 0.0};
+        }
     }
+}
+
+// The first forward pass's registers at L = 4096: v[q][b] = element
+// pos1(t, q, b) = t + 256 (4 q + b) for q < 2.
+__device__ __forceinline__ void load_rows4096(const FftConvArgs& a, int r0, bool two, int t,
+                                              double2 (&v)[4][4])
+{
+    load_rows<8>(a, r0, two, t, &v[0][0]);
 }
 
 // Moves the thread's 16 elements from pattern PW to pattern PR through LDS:
@@ -728,6 +740,308 @@ __global__ __launch_bounds__(kF16Threads, 3) void fft_conv4096_real_kernel(FftCo
                 store_sample(a, r0, p, v[q][b].x);
                 if (two) store_sample(a, r1, p, v[q][b].y);
             }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// L = 2560 = 10 x 16 x 16, for rows of 513 to 1280 samples (2W - 1 <= 2560).
+//
+// With n = n1 + 256 n2 and k = 10 k1 + k2 (n1, k1 < 256; n2, k2 < 10) and
+// w = exp(-2 pi i / 2560), w^(n k) = w256^(n1 k1) w^(n1 k2) w10^(n2 k2): the
+// forward transform is a first pass of 10-point DFTs over n2 (group n1 holds
+// the elements n1 + 256 n2), output k2 times w^(n1 k2) and left at position
+// n1 + 256 k2, followed by a 256-point transform over n1 in each block of
+// 256 positions.  Those are the second and third radix-16 passes of the
+// L = 4096 kernel (the same pass16 stages at Ns = 256 and 16, on the kFftMax
+// table: w256^j = w4096^(16 j)), so bin k ends at position 256 k2 + r(k1),
+// r reversing the base-4 digits of k1.  The spectrum kernel runs the same
+// passes, and the product is again position by position.  The inverse
+// mirrors the forward transform.
+//
+// Samples sit at n < W <= 1280, i.e. n2 < 5: the first pass's DFTs have five
+// non-zero inputs, and the last pass only forms its outputs n2 < 5.  A
+// 10-point DFT is two 5-point ones: with inputs x[0..4] only, Y[2m] =
+// DFT5(x)[m] and Y[2m+1] = DFT5(x[n] w10^n)[m]; in general, with A and B the
+// DFTs of the even and odd inputs, Y[k] = A[k] + w10^k B[k] and Y[k+5] =
+// A[k] - w10^k B[k].  Per row pair this is ~0.6 of the L = 4096 kernel's
+// arithmetic.
+//
+// One workgroup of 256 threads per row pair: thread t runs group t of the
+// 10-point passes, threads t < 160 the radix-16 passes (thread 16 h + j:
+// group j of block h, the positions of pos2 and pos3 above).  Block h is
+// touched in those passes by threads 16 h .. 16 h + 15 only, which lie in
+// one wave, and the LDS operations of a wave take effect in order, so the
+// exchanges between the two radix-16 passes need no workgroup barrier.  The
+// exchanges to and from the 10-point passes cross waves: one barrier each,
+// with a double2 per position.
+constexpr int kT2560 = kL2560 / 16;  // threads of the radix-16 passes
+
+// LDS slot of position p: the low four bits of p XORed with bits 4..7, a
+// permutation inside each run of 16 positions (so each block of 256 keeps
+// its slots) under which the three access patterns (t + 256 k, pos2, pos3)
+// hit distinct banks, with no padding: 40 KiB, four workgroups per CU
+// (padded like qx, 42.5 KiB and three: 3.26 against 3.00 ms for fdk512's
+// pre-filter).
+__device__ __forceinline__ int sx(int p) { return p ^ ((p >> 4) & 15); }
+
+// Orders the wave's LDS accesses before the barrier against those after it
+// (LDS operations of one wave take effect in issue order; this keeps the
+// compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Roots10 {
+    double2 w1, w2, w3, w4;  // w10^k = w^(256 k); w5 = w10^2
+};
+__device__ __forceinline__ Roots10 roots10(const double2* __restrict__ tw)
+{
+    return {tw[256], tw[512], tw[768], tw[1024]};
+}
+
+// In-place 5-point DFT, forward (w5 = exp(-2 pi i / 5)) or inverse
+// (conjugate roots, unscaled): the pairs x1 +- x4 and x2 +- x3 share the
+// cosines cos(2 pi / 5), cos(4 pi / 5) and the sines.
+template <bool INV>
+__device__ __forceinline__ void dft5(double2& x0, double2& x1, double2& x2, double2& x3,
+                                     double2& x4, const Roots10& r)
+{
+    const double c1 = r.w2.x, s1 = -r.w2.y, c2 = r.w4.x, s2 = -r.w4.y;
+    const double2 t1 = cadd(x1, x4), t2 = cadd(x2, x3), t3 = csub(x1, x4), t4 = csub(x2, x3);
+    const double2 a1 = {fma(c2, t2.x, fma(c1, t1.x, x0.x)), fma(c2, t2.y, fma(c1, t1.y, x0.y))};
+    const double2 a2 = {fma(c1, t2.x, fma(c2, t1.x, x0.x)), fma(c1, t2.y, fma(c2, t1.y, x0.y))};
+    const double2 b1 = {fma(s2, t4.x, s1 * t3.x), fma(s2, t4.y, s1 * t3.y)};
+    const double2 b2 = {fma(-s1, t4.x, s2 * t3.x), fma(-s1, t4.y, s2 * t3.y)};
+    x0 = cadd(x0, cadd(t1, t2));
+    const double2 m1 = {b1.y, -b1.x}, m2 = {b2.y, -b2.x};  // -i b
+    if (!INV) {
+        x1 = cadd(a1, m1);
+        x4 = csub(a1, m1);
+        x2 = cadd(a2, m2);
+        x3 = csub(a2, m2);
+    } else {
+        x1 = csub(a1, m1);
+        x4 = cadd(a1, m1);
+        x2 = csub(a2, m2);
+        x3 = cadd(a2, m2);
+    }
+}
+
+// y[k] *= w^(g k) (CONJ: its conjugate), k = 1..9, the powers formed from
+// w^g in FP64 (a few units in its last place)
+template <bool CONJ>
+__device__ __forceinline__ void twiddle10(double2 (&y)[10], int g,
+                                          const double2* __restrict__ tw2560)
+{
+    const double2 u1 = tw2560[g];
+    const double2 u2 = cmul(u1, u1), u3 = cmul(u2, u1), u4 = cmul(u2, u2);
+    const double2 u5 = cmul(u4, u1), u6 = cmul(u3, u3), u8 = cmul(u4, u4);
+    const double2 u7 = cmul(u6, u1), u9 = cmul(u8, u1);
+    const double2 u[9] = {u1, u2, u3, u4, u5, u6, u7, u8, u9};
+#pragma unroll
+    for (int k = 1; k < 10; ++k) y[k] = CONJ ? cmulc(y[k], u[k - 1]) : cmul(y[k], u[k - 1]);
+}
+
+// The first forward pass for group g: y[k] = element g + 256 k on entry
+// (PRUNED: y[5..9] are zero), DFT10 output k times w^(g k) on exit.
+template <bool PRUNED>
+__device__ __forceinline__ void r10_fwd(double2 (&y)[10], int g, const Roots10& r,
+                                        const double2* __restrict__ tw2560)
+{
+    if (PRUNED) {
+        double2 o0 = y[0], o1 = cmul(y[1], r.w1), o2 = cmul(y[2], r.w2), o3 = cmul(y[3], r.w3),
+                o4 = cmul(y[4], r.w4);
+        double2 e0 = y[0], e1 = y[1], e2 = y[2], e3 = y[3], e4 = y[4];
+        dft5<false>(e0, e1, e2, e3, e4, r);
+        dft5<false>(o0, o1, o2, o3, o4, r);
+        y[0] = e0, y[1] = o0, y[2] = e1, y[3] = o1, y[4] = e2;
+        y[5] = o2, y[6] = e3, y[7] = o3, y[8] = e4, y[9] = o4;
+    } else {
+        double2 a0 = y[0], a1 = y[2], a2 = y[4], a3 = y[6], a4 = y[8];
+        double2 b0 = y[1], b1 = y[3], b2 = y[5], b3 = y[7], b4 = y[9];
+        dft5<false>(a0, a1, a2, a3, a4, r);
+        dft5<false>(b0, b1, b2, b3, b4, r);
+        b1 = cmul(b1, r.w1);
+        b2 = cmul(b2, r.w2);
+        b3 = cmul(b3, r.w3);
+        b4 = cmul(b4, r.w4);
+        y[0] = cadd(a0, b0), y[5] = csub(a0, b0);
+        y[1] = cadd(a1, b1), y[6] = csub(a1, b1);
+        y[2] = cadd(a2, b2), y[7] = csub(a2, b2);
+        y[3] = cadd(a3, b3), y[8] = csub(a3, b3);
+        y[4] = cadd(a4, b4), y[9] = csub(a4, b4);
+    }
+    twiddle10<false>(y, g, tw2560);
+}
+
+// The inverse of r10_fwd (times 10) for outputs n2 < 5: y[k] = the
+// transform at g + 256 k on entry, y[n] = element g + 256 n (n < 5) on exit.
+__device__ __forceinline__ void r10_inv(double2 (&y)[10], int g, const Roots10& r,
+                                        const double2* __restrict__ tw2560)
+{
+    twiddle10<true>(y, g, tw2560);
+    double2 a0 = y[0], a1 = y[2], a2 = y[4], a3 = y[6], a4 = y[8];
+    double2 b0 = y[1], b1 = y[3], b2 = y[5], b3 = y[7], b4 = y[9];
+    dft5<true>(a0, a1, a2, a3, a4, r);
+    dft5<true>(b0, b1, b2, b3, b4, r);
+    y[0] = cadd(a0, b0);
+    y[1] = cadd(a1, cmulc(b1, r.w1));
+    y[2] = cadd(a2, cmulc(b2, r.w2));
+    y[3] = cadd(a3, cmulc(b3, r.w3));
+    y[4] = cadd(a4, cmulc(b4, r.w4));
+}
+
+// The radix-16 passes of thread t < kT2560 between the two cross-wave
+// exchanges: forward passes 2 and 3 from the pos2 positions, the product
+// with the spectrum (REAL: real values stored as doubles), the inverse
+// passes 3 and 2, back to the pos2 positions.
+template <bool REAL>
+__device__ __forceinline__ void middle2560(double2* x, const FftConvArgs& a, int t)
+{
+    const double2* __restrict__ tw = a.tw;
+    const Roots16 c = roots16(tw);
+    double2 v[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[q][b] = x[sx(pos2(t, q, b))];
+    r16_fwd<false, false>(v, 16 * (t & 15), c, tw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) x[sx(pos2(t, q, b))] = v[q][b];
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[q][b] = x[sx(pos3(t, q, b))];
+    r16_fwd<false, true>(v, 0, c, tw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = (4 * q + b) * kT2560 + t;
+            if (REAL) {
+                const double h = ((const double*)a.spectrum)[i];
+                v[q][b] = {v[q][b].x * h, v[q][b].y * h};
+            } else {
+                v[q][b] = cmul(v[q][b], a.spectrum[i]);
+            }
+        }
+    r16_inv<false, true>(v, 0, c, tw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) x[sx(pos3(t, q, b))] = v[q][b];
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[q][b] = x[sx(pos2(t, q, b))];
+    r16_inv<false, false>(v, 16 * (t & 15), c, tw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) x[sx(pos2(t, q, b))] = v[q][b];
+}
+
+// Rows 2b and 2b + 1 (if any) of the call; a.L == kL2560 (W <= 1280).
+// (Four waves per SIMD; the complex-spectrum kernel fitted to four spills
+// a few registers and takes three.)
+template <bool REAL>
+__global__ __launch_bounds__(256, REAL ? 4 : 3) void fft_conv2560_kernel(FftConvArgs a)
+{
+    __shared__ double2 x[kL2560];
+    const int t = threadIdx.x;
+    const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
+    const bool two = r1 < a.rows;
+    const double2* __restrict__ tw2560 = a.tw2560;
+    const Roots10 r = roots10(tw2560);
+    // (each loop runs once, g = t: written as loops, the kernel fits four
+    // waves per SIMD without spilling; straight-line, it spilled 76 bytes)
+    for (int g = t; g < 256; g += 256) {
+        double2 y[10];
+        load_rows<5>(a, r0, two, g, y);
+#pragma unroll
+        for (int k = 5; k < 10; ++k) y[k] = {0.0, 0.0};
+        r10_fwd<true>(y, g, r, tw2560);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) x[sx(g + 256 * k)] = y[k];
+    }
+    __syncthreads();
+    if (t < kT2560) middle2560<REAL>(x, a, t);
+    __syncthreads();
+    for (int g = t; g < 256; g += 256) {
+        double2 y[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) y[k] = x[sx(g + 256 * k)];
+        r10_inv(y, g, r, tw2560);
+#pragma unroll
+        for (int n = 0; n < 5; ++n) {
+            const int p = g + 256 * n;
+            if (p < a.W) {
+                store_sample(a, r0, p, y[n].x);
+                if (two) store_sample(a, r1, p, y[n].y);
+            }
+        }
+    }
+}
+
+// The taps' spectrum at L = kL2560 through the same passes, times scale / L,
+// stored where thread t's register (q, b) of the radix-16 passes reads it:
+// (4 q + b) kT2560 + t (REAL: the real parts as doubles; the Ram-Lak taps
+// are even, so their spectrum is real).
+template <bool REAL>
+__global__ __launch_bounds__(256) void fft_spectrum2560_kernel(FftConvArgs a)
+{
+    __shared__ double2 x[kL2560];
+    const int t = threadIdx.x;
+    const double2* __restrict__ tw2560 = a.tw2560;
+    const Roots10 r = roots10(tw2560);
+    double2 y[10];
+    // the taps at n mod L: positions [0, W) and (L - W, L)
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        const int p = t + 256 * k;
+        const int n = p < a.W ? p : p - kL2560;
+        y[k] = {(p < a.W || p > kL2560 - a.W) ? conv_tap(a, n) : 0.0, 0.0};
+    }
+    r10_fwd<false>(y, t, r, tw2560);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) x[sx(t + 256 * k)] = y[k];
+    __syncthreads();
+    if (t >= kT2560) return;
+    const double2* __restrict__ tw = a.tw;
+    const Roots16 c = roots16(tw);
+    double2 v[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[q][b] = x[sx(pos2(t, q, b))];
+    r16_fwd<false, false>(v, 16 * (t & 15), c, tw);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) x[sx(pos2(t, q, b))] = v[q][b];
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[q][b] = x[sx(pos3(t, q, b))];
+    r16_fwd<false, true>(v, 0, c, tw);
+    const double f = a.scale / (double)kL2560;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = (4 * q + b) * kT2560 + t;
+            if (REAL)
+                ((double*)a.spectrum)[i] = v[q][b].x * f;
+            else
+                a.spectrum[i] = {v[q][b].x * f, v[q][b].y * f};
         }
 }
 
@@ -895,7 +1209,8 @@ size_t fft_xcorr_workspace(int K)
 
 hipError_t launch_fft_xcorr(const FftXcorrArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw);
+    hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw,
+                       (double2*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.L == kFftMax) {
@@ -917,7 +1232,9 @@ hipError_t launch_fft_xcorr(const FftXcorrArgs& a, hipStream_t s)
 
 hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw);
+    const bool mixed = a.L == kL2560;
+    hipLaunchKernelGGL(fft_twiddle_kernel, dim3(kFftMax / 256), dim3(256), 0, s, a.tw,
+                       mixed ? a.tw2560 : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.weighted) {
@@ -927,10 +1244,21 @@ hipError_t launch_fft_conv(const FftConvArgs& a, hipStream_t s)
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fft_spectrum_kernel, dim3(1), dim3(kFftThreads), 0, s, a);
+    if (mixed && !a.taps)
+        hipLaunchKernelGGL(fft_spectrum2560_kernel<true>, dim3(1), dim3(256), 0, s, a);
+    else if (mixed)
+        hipLaunchKernelGGL(fft_spectrum2560_kernel<false>, dim3(1), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(fft_spectrum_kernel, dim3(1), dim3(kFftThreads), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (a.L == kFftMax && !a.taps)
+    if (mixed && !a.taps)
+        hipLaunchKernelGGL(fft_conv2560_kernel<true>, dim3((a.rows + 1) / 2),
+                           dim3(256), 0, s, a);
+    else if (mixed)
+        hipLaunchKernelGGL(fft_conv2560_kernel<false>, dim3((a.rows + 1) / 2),
+                           dim3(256), 0, s, a);
+    else if (a.L == kFftMax && !a.taps)
         hipLaunchKernelGGL(fft_conv4096_real_kernel, dim3((a.rows + 1) / 2), dim3(kF16Threads), 0,
                            s, a);
     else if (a.L == kFftMax)

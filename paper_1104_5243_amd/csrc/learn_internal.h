@@ -11,13 +11,17 @@ namespace fdk {
 
 // FFT row convolution (fft_kernels.hip).
 constexpr int kFftMax = 4096;  // largest transform: rows of up to 2048 samples
+constexpr int kL2560 = 2560;   // mixed-radix transform (10 x 16 x 16): rows of 513..1280
 struct FftConvArgs {
     float* out;
     const float* in;
     int rows, W, H;       // H: detector rows per view (weighted input only)
-    int L, log2L;         // transform length, a power of 2 >= max(4, 2W - 1)
+    // transform length >= max(4, 2W - 1): a power of 2 (log2L its log), or
+    // kL2560 (log2L unused)
+    int L, log2L;
     double2* spectrum;    // L entries, written by the spectrum kernel
     double2* tw;          // kFftMax twiddles, written by the twiddle kernel
+    double2* tw2560;      // kL2560 twiddles (L == kL2560 only)
     // taps h[n], -(W-1) <= n <= W-1: Ram-Lak at spacing tau if taps is null,
     // else h[n] = taps[pad - n] (reversed if transpose); all scaled by scale
     const float* taps;

@@ -166,10 +166,11 @@ def test_conv_long_forward_wgrad(env, W, rows):
     assert rel(dh.cpu().numpy(), rdh3[0, 0]) <= 1e-6
 
 
-@pytest.mark.parametrize("W,rows", [(1300, 5), (2048, 2)])
+@pytest.mark.parametrize("W,rows", [(1280, 3), (1300, 5), (2048, 2)])
 def test_conv_long_register_fft(env, W, rows):
-    """Rows of 1025..2048 samples (like those of 513..1024) take the L = 4096 FFT kernel that keeps
-    its passes in registers: forward with bias and accumulation, and the
+    """Rows of 513..1280 samples take the L = 2560 FFT kernel, rows of
+    1281..2048 the L = 4096 one, both keeping their passes in registers
+    (complex spectrum of learned taps): forward with bias and accumulation, and the
     transposed call.  The adjoint of the correlation with taps w at offset
     pad is the correlation with the reversed taps at offset K - 1 - pad."""
     torch, fdk, GL, dev = env

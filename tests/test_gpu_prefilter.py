@@ -33,9 +33,11 @@ def _gpu_prefilter(fdk, torch, dev, li, g, full_scan=False):
     return out
 
 
+# W = 513..1280 take the L = 2560 kernel (1248, 624, 513, 1025, 1280 and an
+# odd row count), 1281..2048 the L = 4096 one, shorter rows the general one
 @pytest.mark.parametrize("shape", [(6, 960, 1248), (5, 480, 624), (3, 7, 9), (3, 5, 2048),
                                    (3, 4, 1), (4, 3, 2), (3, 9, 513),
-                                   (3, 3, 1025)])
+                                   (3, 3, 1025), (3, 5, 1280), (3, 3, 1281)])
 def test_prefilter_parity(env, shape):
     torch, fdk, dev = env
     V, H, W = shape
