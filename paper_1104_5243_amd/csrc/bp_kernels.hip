@@ -364,7 +364,7 @@ static_assert(fused_z(kF32) % kGroup == 0 && fused_z(kF16) % kGroup == 0,
 // outside the plane gives a byte offset outside the buffer's range, which
 // reads as zero (the host has bounded the rows so that the offset cannot
 // wrap into the plane).
-template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV, bool CLAMP = true>
+template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV>
 __device__ __forceinline__ void accumulate_view(
     const FusedArgs& A, float uc, float vc, float wc, float su_t, float su_r, float su2,
     float sv_t, float sv_r, float sv2, float sw_t, float sw_r, float sw2, int lo_u, int hi_u,
@@ -393,8 +393,8 @@ __device__ __forceinline__ void accumulate_view(
             // part 2
             au[q] = __builtin_amdgcn_fractf(u);
             av[q] = __builtin_amdgcn_fractf(v);
-            const int ju = CLAMP ? med3_i32(cvt_floor(u), lo_u, hi_u) : cvt_floor(u);
-            const int jv = CLAMP && VCLAMP ? med3_i32(cvt_floor(v), lo_v, hi_v) : cvt_floor(v);
+            const int ju = med3_i32(cvt_floor(u), lo_u, hi_u);
+            const int jv = VCLAMP ? med3_i32(cvt_floor(v), lo_v, hi_v) : cvt_floor(v);
             const uint32_t off = (uint32_t)(mad_i24_ub(jv, Wp, ju) + base) * kElem;
             if constexpr (kIsF32)
                 load_taps<LAYOUT>(TT{}, rsrc, off, row_bytes, tl[q], tr[q], bl[q], br[q]);
@@ -424,12 +424,6 @@ __device__ __forceinline__ void accumulate_view(
         }
     }
 }
-
-// a second copy of the view's voxel loop without tap clamps, taken by the
-// views whose every tap index of the box lies inside the clamp range
-#ifndef FDK_INSIDE
-#define FDK_INSIDE 0
-#endif
 
 // waves per SIMD the register budget is fitted to (512 VGPRs / 8 = 64)
 #ifndef FDK_MIN_WAVES
@@ -504,15 +498,10 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     for (int j0 = 0; j0 < A.count; j0 += 64) {
         // lane L: the anchor of view j0 + L; WCHECK batches (some voxel may
         // have w <= 0) keep a_u = a_v = 0 and skip nothing
-        uint64_t skip, inside;
+        uint64_t skip;
         {
             const Anchor an = make_anchor<!WCHECK>(A, j0 + lane, bf);
             skip = __ballot(an.skip);
-            // every tap index of the box within the clamp range already
-            // (half a pixel of margin): the view needs no clamps
-            inside = __ballot(!WCHECK && an.wmin > 0.0f &&
-                              an.umin >= (float)A.lo_iu + 0.5f && an.umax <= (float)A.hi_iu + 0.5f &&
-                              an.vmin >= (float)A.lo_iv + 0.5f && an.vmax <= (float)A.hi_iv + 0.5f);
             const int base = an.av * A.Wp + an.au + A.origin_off;
             float* row = an_rows[lane];
             *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
@@ -537,14 +526,6 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
             const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
             // (the w row's z slope from LDS, a vector register: the slice
             // FMAs take their slice index as an inline literal)
-#if FDK_INSIDE
-            if ((inside >> jj) & 1)
-                accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV, false>(
-                    A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
-                    __builtin_bit_cast(float, r2.x), m[8], m[9], r3.z, 0, 0, 0, 0, r2.y, d_t, d_r,
-                    rsrc, acc);
-            else
-#endif
             accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV>(
                 A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, __builtin_bit_cast(float, r2.x),
                 m[8], m[9], r3.z, r2.z, r2.w, __builtin_bit_cast(int, r3.x),

@@ -140,15 +140,15 @@ __host__ __device__ constexpr int pitch2(int n) { return ((n + 29) / 32) * 32 + 
 // all of a thread's global loads into registers, put() stores them.  A
 // kernel that walks chunks fetches the next chunk before computing on the
 // current one, so the loads' latency hides behind that work.
-template <int ROWS, int VALID, int SPAN, int PITCH>
+template <int ROWS, int VALID, int SPAN, int PITCH, int NTH = 256>
 struct TileCopy {
-    static constexpr int kN = (ROWS * SPAN + 255) / 256;
+    static constexpr int kN = (ROWS * SPAN + NTH - 1) / NTH;
     float r[kN];
     __device__ __forceinline__ void fetch(const float* src, int W, int j_first)
     {
 #pragma unroll
         for (int k = 0; k < kN; ++k) {
-            const int e = threadIdx.x + 256 * k;
+            const int e = threadIdx.x + NTH * k;
             const int row = e / SPAN, sp = e - row * SPAN;
             const int j = j_first + sp;
             r[k] = (e < ROWS * SPAN && row < VALID && j >= 0 && j < W)
@@ -159,108 +159,141 @@ struct TileCopy {
     {
 #pragma unroll
         for (int k = 0; k < kN; ++k) {
-            const int e = threadIdx.x + 256 * k;
+            const int e = threadIdx.x + NTH * k;
             const int row = e / SPAN, sp = e - row * SPAN;
             if (e < ROWS * SPAN) dst[row * PITCH + sp] = r[k];
         }
     }
 };
 
-// Convolution: a block owns 128 positions of one row at a time (wave w:
-// positions 32 w .. 32 w + 31, two 16-wide n-tiles) for all output
+// Convolution: a block of 8 waves owns 128 positions of one row at a time
+// (wave w: positions 16 w .. 16 w + 15, one 16-wide n-tile) for all output
 // channels (two 16-wide m-tiles); the weights, stored as A fragments, stay
-// in LDS for the block's lifetime; it walks the chunks of all rows.
+// in LDS for the block's lifetime; it walks the chunks of all rows, with
+// two input tiles in turn.  (Learned filter at 128^3, 32 -> 32 layer: 4
+// waves with two n-tiles each and one tile, 3.55 ms; two tiles, 3.47; 8
+// waves, 100 VGPRs, four per SIMD: 3.10-3.20.)
 template <int CIN, int COUT, int KT>
 struct ConvMfma {
-    static constexpr int kChunk = 128;
+    static constexpr int kWaves = 8;
+    static constexpr int kChunk = 16 * kWaves;
     static constexpr int kMT = COUT / 16;
     static constexpr int kC4 = CIN / 4;
     static constexpr int kSteps = kC4 * KT;
     static constexpr int kSpan = kChunk + KT - 1;
     static constexpr int kPitch = pitch16(kSpan);
     static constexpr int kWeights = kMT * kSteps * 64;
-    static constexpr size_t lds_bytes() { return (size_t)(kWeights + CIN * kPitch) * 4; }
+    static constexpr size_t lds_bytes() { return (size_t)(kWeights + 2 * CIN * kPitch) * 4; }
     static_assert(CIN % 4 == 0 && COUT % 16 == 0, "channel counts");
 };
 
-template <int CIN, int COUT, int KT>
-__global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chunks_per_row,
+// OLD: the call reads the output's values (mask or accumulate).
+template <int CIN, int COUT, int KT, bool OLD>
+__global__ __launch_bounds__((64 * ConvMfma<CIN, COUT, KT>::kWaves)) void conv_mfma_kernel(LearnConvArgs a, int chunks_per_row,
                                                         int total_chunks)
 {
     using C = ConvMfma<CIN, COUT, KT>;
+    constexpr int NT = 64 * C::kWaves;  // threads
+    constexpr int NTW = 1;              // 16-wide n-tiles per wave
     extern __shared__ float lds[];
     float* wl = lds;                 // A fragments: [mt][step][lane]
-    float* xs = lds + C::kWeights;   // input tile: [ci][kPitch]
+    float* xs = lds + C::kWeights;   // two input tiles: [buffer][ci][kPitch]
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    for (int e = threadIdx.x; e < C::kWeights; e += 256) {
+    for (int e = threadIdx.x; e < C::kWeights; e += NT) {
         const int ll = e & 63, f = e >> 6;
         const int mt = f / C::kSteps, st = f - mt * C::kSteps;
         const int c4 = st / KT, t = st - c4 * KT;
         wl[e] = conv_weight(a, mt * 16 + (ll & 15), 4 * c4 + (ll >> 4), t);
     }
-    const float* xb = xs + (l >> 4) * C::kPitch + w * 32 + (l & 15);
-    TileCopy<CIN, CIN, C::kSpan, C::kPitch> tile;
+    TileCopy<CIN, CIN, C::kSpan, C::kPitch, NT> tile;
     auto fetch = [&](int c) {
         const int row = c / chunks_per_row;
         const int j0 = (c - row * chunks_per_row) * C::kChunk;
         tile.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
     };
-    if ((int)blockIdx.x < total_chunks) fetch(blockIdx.x);
-    for (int c = blockIdx.x; c < total_chunks; c += gridDim.x) {
+    // the biases of the lane's output channels, read once (read per store,
+    // the compiler waited for every outstanding load, the next tile's
+    // included, at each)
+    float bias[C::kMT][4];
+#pragma unroll
+    for (int mt = 0; mt < C::kMT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias[mt][i] = a.bias ? a.bias[mt * 16 + 4 * (l >> 4) + i] : 0.0f;
+    // Double-buffered tiles: while the block computes chunk c from one
+    // buffer, chunk c + grid (fetched into registers during chunk c - grid)
+    // goes into the other, and chunk c + 2 grid is fetched; one barrier per
+    // chunk.
+    const int G = gridDim.x;  // <= total_chunks (the host's grid)
+    fetch(blockIdx.x);
+    tile.put(xs);
+    fetch(min((int)blockIdx.x + G, total_chunks - 1));
+    int buf = 0;
+    for (int c = blockIdx.x; c < total_chunks; c += G, buf ^= 1) {
         const int row = c / chunks_per_row;
         const int j0 = (c - row * chunks_per_row) * C::kChunk;
-        __syncthreads();  // the previous chunk's fragment reads are done
-        tile.put(xs);
-        __syncthreads();
-        if (c + (int)gridDim.x < total_chunks) fetch(c + gridDim.x);
+        // values the output holds (mask, accumulate), used by the stores
+        // only: read first, so that the stores wait for them and not for the
+        // next tile's loads issued after; unguarded, with the column clamped
+        // into the row (the stores skip the columns past W).  (Guarded per
+        // load, after the tile's loads, the compiler waited for all of them
+        // here: masked adjoint at 128^3, 4.2 against 3.3 ms unmasked.)
         float* out = a.out + (size_t)row * COUT * a.W;
-        // values the output holds (mask, accumulate), read before the MFMA work
-        float old[C::kMT][2][4];
-        if (a.mask || a.accumulate) {
+        float old[C::kMT][NTW][4];
+        if (OLD) {
 #pragma unroll
             for (int mt = 0; mt < C::kMT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    const int j = j0 + w * 32 + nt * 16 + (l & 15);
+                for (int nt = 0; nt < NTW; ++nt) {
+                    const int jc = min(j0 + w * 16 * NTW + nt * 16 + (l & 15), a.W - 1);
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        old[mt][nt][i] =
-                            j < a.W ? out[(size_t)(mt * 16 + 4 * (l >> 4) + i) * a.W + j] : 0.0f;
+                        old[mt][nt][i] = out[(size_t)(mt * 16 + 4 * (l >> 4) + i) * a.W + jc];
                 }
         }
-        mf4 acc[C::kMT][2];
+        // chunk c's tile is complete, and every wave is done with the other
+        // buffer (chunk c - G's fragment reads)
+        __syncthreads();
+        // (the fetch is unconditional, of a valid chunk at the end: a load
+        // under a branch makes the compiler wait for every outstanding load
+        // where the branches join)
+        if (c + G < total_chunks) tile.put(xs + (buf ^ 1) * CIN * C::kPitch);
+        fetch(min(c + 2 * G, total_chunks - 1));
+        const float* xb = xs + buf * CIN * C::kPitch + (l >> 4) * C::kPitch + w * 16 * NTW + (l & 15);
+        mf4 acc[C::kMT][NTW];
 #pragma unroll
         for (int mt = 0; mt < C::kMT; ++mt)
-            acc[mt][0] = acc[mt][1] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = mf4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int c4 = 0; c4 < C::kC4; ++c4) {
 #pragma unroll
             for (int t = 0; t < KT; ++t) {
                 const int st = c4 * KT + t;
-                const float b0 = xb[c4 * 4 * C::kPitch + t];
-                const float b1 = xb[c4 * 4 * C::kPitch + t + 16];
+                float bv[NTW];
+#pragma unroll
+                for (int nt = 0; nt < NTW; ++nt) bv[nt] = xb[c4 * 4 * C::kPitch + t + 16 * nt];
 #pragma unroll
                 for (int mt = 0; mt < C::kMT; ++mt) {
                     const float av = wl[(mt * C::kSteps + st) * 64 + l];
-                    acc[mt][0] = mfma16x16x4(av, b0, acc[mt][0]);
-                    acc[mt][1] = mfma16x16x4(av, b1, acc[mt][1]);
+#pragma unroll
+                    for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = mfma16x16x4(av, bv[nt], acc[mt][nt]);
                 }
             }
         }
 #pragma unroll
         for (int mt = 0; mt < C::kMT; ++mt) {
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                const int j = j0 + w * 32 + nt * 16 + (l & 15);
+            for (int nt = 0; nt < NTW; ++nt) {
+                const int j = j0 + w * 16 * NTW + nt * 16 + (l & 15);
                 if (j >= a.W) continue;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int co = mt * 16 + 4 * (l >> 4) + i;
-                    float v = acc[mt][nt][i] + (a.bias ? a.bias[co] : 0.0f);
-                    if (a.accumulate) v += old[mt][nt][i];
+                    float v = acc[mt][nt][i] + bias[mt][i];
+                    if (OLD && a.accumulate) v += old[mt][nt][i];
                     if (a.relu) v = fmaxf(v, 0.0f);
-                    if (a.mask) v = old[mt][nt][i] > 0.0f ? v : 0.0f;
+                    if (OLD && a.mask) v = old[mt][nt][i] > 0.0f ? v : 0.0f;
                     out[(size_t)co * a.W + j] = v;
                 }
             }
@@ -269,35 +302,38 @@ __global__ __launch_bounds__(256) void conv_mfma_kernel(LearnConvArgs a, int chu
 }
 
 // Weight gradient: a block walks chunks of 64 positions (16 k-steps); the
-// 32 x 288 result (columns n = t * CIN + ci) is split over the 4 waves by
-// n-tile (wave w: n-tiles w, w + 4, ...).  The MFMA accumulators are added
+// 32 x 288 result (columns n = t * CIN + ci) is split over the NW waves by
+// n-tile (wave w: n-tiles w, w + NW, ...).  The MFMA accumulators are added
 // into FP64 sums after every chunk, the bias gradient is summed in FP64,
 // and the per-block sums go to the workspace for the fixed-order reduction.
-template <int CIN, int COUT, int KT>
+// (32 -> 32 at 128^3: 4 waves at two per SIMD, 3.88 ms; 8 waves fitted to
+// four per SIMD, 3.56 ms, bit-identical: each n-tile's sums stay in one
+// wave.)
+template <int CIN, int COUT, int KT, int NW = 4>
 struct WgradMfma {
     static constexpr int kChunk = 64;
     static constexpr int kMT = (COUT + 15) / 16;       // m-tiles (rows past COUT are zero)
     static constexpr int kNN = CIN * KT;               // columns n = t * CIN + ci
     static constexpr int kNT = (kNN + 15) / 16;        // n-tiles (columns past kNN are zero)
-    static constexpr int kNTW = (kNT + 3) / 4;         // n-tiles per wave (at most)
+    static constexpr int kNTW = (kNT + NW - 1) / NW;   // n-tiles per wave (at most)
     static constexpr int kSpan = kChunk + KT - 1;
     static constexpr int kPitchX = pitch2(kSpan);
     static constexpr int kPitchD = pitch2(kChunk);
-    // waves per SIMD the register allocation aims at (fdk128 shapes, ms:
-    // 32->32 6.2 at the default, 4.2 at two waves; 1->32 1.0, 0.84; 32->1
-    // 2.7 at the default, 4.8 at two)
-    static constexpr int kMinWaves = COUT == 1 ? 1 : 2;
+    // waves per SIMD the register allocation aims at (fdk128 shapes, ms, in
+    // 4-wave blocks: 32->32 6.2 at the default, 4.2 at two waves; 1->32 1.0,
+    // 0.84; 32->1 2.7 at the default, 4.8 at two); 8-wave blocks aim at four
+    static constexpr int kMinWaves = NW == 8 ? 4 : COUT == 1 ? 1 : 2;
     static constexpr size_t lds_bytes()
     {
-        return (size_t)(16 * kMT * kPitchD + CIN * kPitchX) * 4 + 256 * sizeof(double);
+        return (size_t)(16 * kMT * kPitchD + CIN * kPitchX) * 4 + 64 * NW * sizeof(double);
     }
 };
 
-template <int CIN, int COUT, int KT>
-__global__ __launch_bounds__(256, (WgradMfma<CIN, COUT, KT>::kMinWaves)) void wgrad_mfma_kernel(LearnGradArgs a, int chunks_per_row,
+template <int CIN, int COUT, int KT, int NW = 4>
+__global__ __launch_bounds__(64 * NW, (WgradMfma<CIN, COUT, KT, NW>::kMinWaves)) void wgrad_mfma_kernel(LearnGradArgs a, int chunks_per_row,
                                                          int total_chunks)
 {
-    using G = WgradMfma<CIN, COUT, KT>;
+    using G = WgradMfma<CIN, COUT, KT, NW>;
     extern __shared__ float lds[];
     float* dy = lds;                               // [co][kPitchD], 16 kMT rows
     float* xs = lds + 16 * G::kMT * G::kPitchD;    // [ci][kPitchX]
@@ -309,7 +345,7 @@ __global__ __launch_bounds__(256, (WgradMfma<CIN, COUT, KT>::kMinWaves)) void wg
     bool bvalid[G::kNTW];
 #pragma unroll
     for (int k = 0; k < G::kNTW; ++k) {
-        const int n = (w + 4 * k) * 16 + (l & 15);
+        const int n = (w + NW * k) * 16 + (l & 15);
         bvalid[k] = n < G::kNN;
         const int t = n / CIN, ci = n - t * CIN;
         boff[k] = bvalid[k] ? ci * G::kPitchX + t + (l >> 4) : 0;
@@ -326,8 +362,8 @@ __global__ __launch_bounds__(256, (WgradMfma<CIN, COUT, KT>::kMinWaves)) void wg
             for (int i = 0; i < 4; ++i) sum[mt][k][i] = 0.0;
         }
     double accb = 0.0;  // bias gradient: thread sums co = tid / 8, positions (tid % 8) * 8 ..
-    TileCopy<16 * G::kMT, COUT, G::kChunk, G::kPitchD> dtile;
-    TileCopy<CIN, CIN, G::kSpan, G::kPitchX> xtile;
+    TileCopy<16 * G::kMT, COUT, G::kChunk, G::kPitchD, 64 * NW> dtile;
+    TileCopy<CIN, CIN, G::kSpan, G::kPitchX, 64 * NW> xtile;
     auto fetch = [&](int c) {
         const int row = c / chunks_per_row;
         const int j0 = (c - row * chunks_per_row) * G::kChunk;
@@ -348,7 +384,7 @@ __global__ __launch_bounds__(256, (WgradMfma<CIN, COUT, KT>::kMinWaves)) void wg
             for (int mt = 0; mt < G::kMT; ++mt) av[mt] = dy[aoff + mt * 16 * G::kPitchD + 4 * st];
 #pragma unroll
             for (int k = 0; k < G::kNTW; ++k) {
-                if (w + 4 * k < G::kNT) {
+                if (w + NW * k < G::kNT) {
                     const float bv = bvalid[k] ? xs[boff[k] + 4 * st] : 0.0f;
 #pragma unroll
                     for (int mt = 0; mt < G::kMT; ++mt) acc[mt][k] = mfma16x16x4(av[mt], bv, acc[mt][k]);
@@ -377,8 +413,8 @@ __global__ __launch_bounds__(256, (WgradMfma<CIN, COUT, KT>::kMinWaves)) void wg
     for (int mt = 0; mt < G::kMT; ++mt)
 #pragma unroll
         for (int k = 0; k < G::kNTW; ++k) {
-            if (w + 4 * k >= G::kNT || !bvalid[k]) continue;
-            const int n = (w + 4 * k) * 16 + (l & 15);
+            if (w + NW * k >= G::kNT || !bvalid[k]) continue;
+            const int n = (w + NW * k) * 16 + (l & 15);
             const int t = n / CIN, ci = n - t * CIN;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -618,8 +654,12 @@ hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s)
         const int cpr = (a.W + C::kChunk - 1) / C::kChunk;
         const int total = a.rows * cpr;
         const int grid = total < 1024 ? total : 1024;
-        hipLaunchKernelGGL((conv_mfma_kernel<32, 32, 9>), dim3(grid), dim3(256), C::lds_bytes(), s,
-                           a, cpr, total);
+        if (a.mask || a.accumulate)
+            hipLaunchKernelGGL((conv_mfma_kernel<32, 32, 9, true>), dim3(grid), dim3(64 * C::kWaves),
+                               C::lds_bytes(), s, a, cpr, total);
+        else
+            hipLaunchKernelGGL((conv_mfma_kernel<32, 32, 9, false>), dim3(grid),
+                               dim3(64 * C::kWaves), C::lds_bytes(), s, a, cpr, total);
     } else if (a.K <= kMaxShortK) {
         dim3 grid((a.W + kShortTile - 1) / kShortTile, a.rows);
         const size_t lds = (size_t)a.cin * (kShortTile + a.K - 1) * sizeof(float);
@@ -737,8 +777,8 @@ hipError_t launch_wgrad(const LearnGradArgs& a, int nblocks, hipStream_t s)
 {
     const int cpr = (a.W + 63) / 64;  // 64-position chunks
     if (mfma_shape(a.cin, a.cout, a.K)) {
-        hipLaunchKernelGGL((wgrad_mfma_kernel<32, 32, 9>), dim3(nblocks), dim3(256),
-                           (WgradMfma<32, 32, 9>::lds_bytes()), s, a, cpr, a.rows * cpr);
+        hipLaunchKernelGGL((wgrad_mfma_kernel<32, 32, 9, 8>), dim3(nblocks), dim3(512),
+                           (WgradMfma<32, 32, 9, 8>::lds_bytes()), s, a, cpr, a.rows * cpr);
     } else if (a.K == 9 && a.cin == 1 && a.cout == 32) {
         hipLaunchKernelGGL((wgrad_mfma_kernel<1, 32, 9>), dim3(nblocks), dim3(256),
                            (WgradMfma<1, 32, 9>::lds_bytes()), s, a, cpr, a.rows * cpr);
