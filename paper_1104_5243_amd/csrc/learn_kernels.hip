@@ -534,12 +534,27 @@ __host__ __device__ constexpr bool mfma_shape(int cin, int cout, int K)
     return cin == 32 && cout == 32 && K == 9;
 }
 
+// The call's weights w(co, ci, t) into LDS at (co * CIN + ci) * KT + t and
+// its biases (0 without) at co, for the block's threads to read at uniform
+// addresses.  (Read from global memory per use, each weight's load was
+// waited for before its FMAs: the narrow layers were bound by those waits.)
+template <int CIN, int COUT, int KT>
+__device__ __forceinline__ void stage_weights(const LearnConvArgs& a, float* wl, float* bl)
+{
+    for (int e = threadIdx.x; e < COUT * CIN * KT; e += blockDim.x) {
+        const int co = e / (CIN * KT), r = e - co * CIN * KT;
+        const int ci = r / KT, t = r - ci * KT;
+        wl[e] = conv_weight(a, co, ci, t);
+    }
+    for (int e = threadIdx.x; e < COUT; e += blockDim.x) bl[e] = a.bias ? a.bias[e] : 0.0f;
+}
+
 // ---------------------------------------------------------------------------
 // narrow layers (one channel in or out, 9 taps): memory-bound
 // ---------------------------------------------------------------------------
 // One thread per output position, 256 positions per block, the input tile
 // (CIN x (256 + KT - 1)) in LDS, its global loads all issued before any is
-// stored; the weights are wave-uniform (compile-time indices, scalar loads).
+// stored; the weights and biases staged in LDS (stage_weights).
 // CIN = 1: the thread forms all COUT outputs from its KT inputs; COUT = 1: it
 // sums CIN x KT products.  With a.mask or a.accumulate the COUT values the
 // output holds are read up front, not one per output store.
@@ -548,6 +563,8 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
 {
     constexpr int kSpan = 256 + KT - 1;
     __shared__ float tile[CIN * kSpan];
+    __shared__ float wl[COUT * CIN * KT];  // w(co, ci, t) at (co * CIN + ci) * KT + t
+    __shared__ float bl[COUT];
     const int row = blockIdx.y;
     const int j0 = blockIdx.x * 256;
     {
@@ -555,6 +572,7 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
         tc.fetch(a.in + (size_t)row * CIN * a.W, a.W, j0 - a.pad);
         tc.put(tile);
     }
+    stage_weights<CIN, COUT, KT>(a, wl, bl);
     const int j = j0 + threadIdx.x;
     float* out = a.out + (size_t)row * COUT * a.W + j;
     float old[COUT];
@@ -571,20 +589,20 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
         for (int t = 0; t < KT; ++t) xv[t] = x[t];
 #pragma unroll
         for (int co = 0; co < COUT; ++co) {
-            float acc = a.bias ? a.bias[co] : 0.0f;
+            float acc = bl[co];
 #pragma unroll
-            for (int t = 0; t < KT; ++t) acc = fmaf(conv_weight(a, co, 0, t), xv[t], acc);
+            for (int t = 0; t < KT; ++t) acc = fmaf(wl[co * KT + t], xv[t], acc);
             if (a.accumulate) acc += old[co];
             if (a.relu) acc = fmaxf(acc, 0.0f);
             if (a.mask) acc = old[co] > 0.0f ? acc : 0.0f;
             out[(size_t)co * a.W] = acc;
         }
     } else {
-        float acc = a.bias ? a.bias[0] : 0.0f;
+        float acc = bl[0];
 #pragma unroll
         for (int ci = 0; ci < CIN; ++ci)
 #pragma unroll
-            for (int t = 0; t < KT; ++t) acc = fmaf(conv_weight(a, 0, ci, t), x[ci * kSpan + t], acc);
+            for (int t = 0; t < KT; ++t) acc = fmaf(wl[ci * KT + t], x[ci * kSpan + t], acc);
         if (a.accumulate) acc += old[0];
         if (a.relu) acc = fmaxf(acc, 0.0f);
         if (a.mask) acc = old[0] > 0.0f ? acc : 0.0f;
@@ -597,9 +615,14 @@ __global__ __launch_bounds__(256) void conv_narrow_kernel(LearnConvArgs a)
 // with its neighbours through the L1) and writes each output channel with
 // one 16-byte store (4-byte stores measured 0.98 ms against 0.56 ms for the
 // 32 channels of 128^3 x 62 views of 624-sample rows).
-template <int COUT, int KT>
+// OLD: the call reads the output's values (mask or accumulate).
+template <int COUT, int KT, bool OLD>
 __global__ __launch_bounds__(256) void conv_narrow1x4_kernel(LearnConvArgs a)
 {
+    __shared__ float wl[COUT * KT];  // w(co, 0, t) at co * KT + t
+    __shared__ float bl[COUT];
+    stage_weights<1, COUT, KT>(a, wl, bl);
+    __syncthreads();
     const int row = blockIdx.y;
     const int j = (blockIdx.x * 256 + threadIdx.x) * 4;
     if (j >= a.W) return;
@@ -611,25 +634,27 @@ __global__ __launch_bounds__(256) void conv_narrow1x4_kernel(LearnConvArgs a)
         const int p = j + t - a.pad;
         xv[t] = (p >= 0 && p < a.W) ? in[p] : 0.0f;
     }
+    // the values the outputs hold (OLD: mask or accumulate), channel co + 1's
+    // read while channel co is computed
+    float4 next = OLD ? *(const float4*)out : float4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int co = 0; co < COUT; ++co) {
-        // the values this channel's outputs hold (mask, accumulate)
-        const float4 old = (a.mask || a.accumulate) ? *(const float4*)(out + (size_t)co * a.W)
-                                                    : float4{0.0f, 0.0f, 0.0f, 0.0f};
-        const float b = a.bias ? a.bias[co] : 0.0f;
+        const float4 old = next;
+        if (OLD) next = *(const float4*)(out + (size_t)min(co + 1, COUT - 1) * a.W);
+        const float b = bl[co];
         float acc[4] = {b, b, b, b};
 #pragma unroll
         for (int t = 0; t < KT; ++t) {
-            const float w = conv_weight(a, co, 0, t);
+            const float w = wl[co * KT + t];
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = fmaf(w, xv[q + t], acc[q]);
         }
         const float ov[4] = {old.x, old.y, old.z, old.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (a.accumulate) acc[q] += ov[q];
+            if (OLD && a.accumulate) acc[q] += ov[q];
             if (a.relu) acc[q] = fmaxf(acc[q], 0.0f);
-            if (a.mask) acc[q] = ov[q] > 0.0f ? acc[q] : 0.0f;
+            if (OLD && a.mask) acc[q] = ov[q] > 0.0f ? acc[q] : 0.0f;
         }
         *(float4*)(out + (size_t)co * a.W) = float4{acc[0], acc[1], acc[2], acc[3]};
     }
@@ -641,8 +666,14 @@ hipError_t launch_conv(const LearnConvArgs& a, hipStream_t s)
         // 16-byte stores need W a multiple of 4 and a 16-byte aligned output
         dim3 grid((a.W + 255) / 256, a.rows);
         if (a.cin == 1 && (a.W & 3) == 0 && ((uintptr_t)a.out & 15) == 0)
-            hipLaunchKernelGGL((conv_narrow1x4_kernel<32, 9>), dim3((a.W + 1023) / 1024, a.rows),
-                               dim3(256), 0, s, a);
+        {
+            if (a.mask || a.accumulate)
+                hipLaunchKernelGGL((conv_narrow1x4_kernel<32, 9, true>),
+                                   dim3((a.W + 1023) / 1024, a.rows), dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((conv_narrow1x4_kernel<32, 9, false>),
+                                   dim3((a.W + 1023) / 1024, a.rows), dim3(256), 0, s, a);
+        }
         else if (a.cin == 1)
             hipLaunchKernelGGL((conv_narrow_kernel<1, 32, 9>), grid, dim3(256), 0, s, a);
         else
