@@ -10,14 +10,15 @@
 // the first row's convolution and the imaginary part the second's.
 //
 // The forward transform is an in-place decimation-in-frequency FFT (radix 4,
-// plus one radix-2 stage when log2 L is odd) whose output is in digit-
-// reversed order; the inverse is the mirrored decimation-in-time FFT, which
-// takes that order and returns natural order.  The taps' spectrum comes from
-// the same forward transform, so it sits in the same order and the product
-// is taken position by position: no reordering pass.  Twiddles come from a
-// table of exp(-2 pi i k / kFftMax), k < kFftMax.  All arithmetic is FP64
-// (the ramp removes each row's mean: its output is a small difference of
-// large terms), rounded once to FP32 on output.
+// plus one radix-2 stage when log2 L is odd; a radix-10 pass first at L =
+// 2560) whose output is in digit-reversed order; the inverse is the mirrored
+// decimation-in-time FFT, which takes that order and returns natural order.
+// The taps' spectrum comes from the same forward transform, so it sits in
+// the same order and the product is taken position by position: no
+// reordering pass.  Twiddles come from a table of exp(-2 pi i k / kFftMax),
+// k < kFftMax (and one of exp(-2 pi i k / 2560) at L = 2560).  All
+// arithmetic is FP64 (the ramp removes each row's mean: its output is a
+// small difference of large terms), rounded once to FP32 on output.
 //
 // Three kernels run the convolution: a general one for power-of-two L (its
 // passes go through LDS, pairs of radix-4 stages at a time), and two that
