@@ -130,7 +130,7 @@ int main(void)
         free(Rb);
     }
     int pts[6 * 3] = {0, 0, 0, N - 1, N - 1, N - 1, 4, 4, 4, 0, N - 1, 3, N - 1, 0, 5, 2, 7, 1};
-    double Rp[6];
+    double Rp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  /* accumulated into: start at zero */
     CHECK(oracle_backproject_points(Rp, pts, 6, N, vs, origin, proj, V, H, W, P) == 0);
     for (int i = 0; i < 6; ++i)
         CHECK(Rp[i] == R[((size_t)pts[3 * i + 2] * N + pts[3 * i + 1]) * N + pts[3 * i]]);
