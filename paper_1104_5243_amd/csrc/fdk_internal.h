@@ -73,6 +73,7 @@ struct FusedArgs {
     int lo_iv, hi_iv;
     // forward projection
     int fp_tile;                   // entries of a workgroup's LDS tile
+    int fp_vparts;                 // workgroups per box (grid y), each with whole chunks of the views
     unsigned long long* acc64;     // count padded planes of 64-bit fixed-point sums
     const unsigned* fp_vmax;       // max |x| of the volume (float bits, device)
     float fp_rmax2;                // >= 1 / w^2 over the volume and the batch's views

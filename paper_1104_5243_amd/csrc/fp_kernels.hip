@@ -326,8 +326,11 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     const float Sg = __builtin_ldexpf(1.0f, kg);
     const int Wp = A.Wp;
     const const_float* mats = as_constant(A.m);
-    unsigned long long* plane = A.acc64;
-    for (int j0 = 0; j0 < A.count; j0 += kFpChunk, plane += kFpChunk * A.plane) {
+    // this workgroup's views: part blockIdx.y of the batch, whole chunks
+    const int per = ((A.count + A.fp_vparts - 1) / A.fp_vparts + kFpChunk - 1) / kFpChunk * kFpChunk;
+    const int jbeg = blockIdx.y * per, jend = min(A.count, jbeg + per);
+    unsigned long long* plane = A.acc64 + (size_t)jbeg * A.plane;
+    for (int j0 = jbeg; j0 < jend; j0 += kFpChunk, plane += kFpChunk * A.plane) {
         if (threadIdx.x < 4 * kFpChunk) {
             // thread (b, view): the anchor of box b for view j0 + view
             const int b = threadIdx.x / kFpChunk, jv = threadIdx.x % kFpChunk;
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
                                                       part ? 1.0f : 0.0f, 0.0f, 0.0f);
         }
         __syncthreads();
-        const int jn = min(kFpChunk, A.count - j0);
+        const int jn = min(kFpChunk, jend - j0);
         for (int jj = 0; jj < jn; ++jj) {
             unsigned long long* pl = plane + (size_t)jj * A.plane;
             // footprint of the boxes that reach the detector
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
 
 hipError_t launch_scatter_lds(const FusedArgs& a, hipStream_t s)
 {
-    dim3 grid(a.tiles_x * a.tiles_y * a.zchunks);
+    dim3 grid(a.tiles_x * a.tiles_y * a.zchunks, a.fp_vparts);
     const size_t lds = (size_t)a.fp_tile * sizeof(int);
     if (a.y_fastest)
         hipLaunchKernelGGL(fp_lds_kernel<true>, grid, dim3(256), lds, s, a);
