@@ -573,13 +573,26 @@ __device__ __forceinline__ void load_rows(const FftConvArgs& a, int r0, bool two
         const double* c1 = a.cosw + (size_t)k1 * a.W;
         const double* p0 = a.parker + (size_t)view0 * a.W;
         const double* p1 = a.parker + (size_t)view1 * a.W;
+        if (view1 == view0) {
+            // (rows of one view, the usual case: one Parker load per sample)
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const int p = t + 256 * k;
-            const int pc = min(p, a.W - 1);
-            const double x0 = (double)in0[pc] * c0[pc] * p0[pc];
-            const double x1 = (double)in1[pc] * c1[pc] * p1[pc];
-            y[k] = p < a.W ? double2{x0, two ? x1 : 0.0} : double2{0.0, 0.0};
+            for (int k = 0; k < NK; ++k) {
+                const int p = t + 256 * k;
+                const int pc = min(p, a.W - 1);
+                const double pw = p0[pc];
+                const double x0 = (double)in0[pc] * c0[pc] * pw;
+                const double x1 = (double)in1[pc] * c1[pc] * pw;
+                y[k] = p < a.W ? double2{x0, two ? x1 : 0.0} : double2{0.0, 0.0};
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const int p = t + 256 * k;
+                const int pc = min(p, a.W - 1);
+                const double x0 = (double)in0[pc] * c0[pc] * p0[pc];
+                const double x1 = (double)in1[pc] * c1[pc] * p1[pc];
+                y[k] = p < a.W ? double2{x0, two ? x1 : 0.0} : double2{0.0, 0.0};
+            }
         }
     } else {
 #pragma unroll
