@@ -260,6 +260,16 @@ int storage_size(int dtype)
     return dtype == FDK_DTYPE_F32 ? 4 : 2;
 }
 
+// The workgroup tiles of the batch's ray axis (A.y_fastest), the grid they
+// make with A.zchunks, and whether that grid takes the XCD remap.
+void set_tiles(FusedArgs& A, int N)
+{
+    const bool yf = A.y_fastest != 0;
+    A.tiles_x = (N + tile_x(yf) - 1) / tile_x(yf);
+    A.tiles_y = (N + tile_y(yf) - 1) / tile_y(yf);
+    const long long blocks = (long long)A.tiles_x * A.tiles_y * A.zchunks;
+    A.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+}
 
 // Launch geometry shared by the backprojection and the forward projection:
 // everything in FusedArgs except the staged planes and the matrices.
@@ -290,11 +300,8 @@ void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long l
     A.hi_iv = H - kv;
     A.origin_off = (kv + kPad) * Wp + (ku + kPad);
     A.c = 0.5f * (float)(N - 1);
-    A.tiles_x = (N + kTileX - 1) / kTileX;
-    A.tiles_y = (N + kTileY - 1) / kTileY;
     A.zchunks = (N + zdepth - 1) / zdepth;
-    const long long blocks = (long long)A.tiles_x * A.tiles_y * A.zchunks;
-    A.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
+    set_tiles(A, N);
 }
 
 // Fold the matrices of views [v0, v0+cnt) into out (cnt x 12 floats, in
@@ -328,6 +335,7 @@ bool fold_batch(FusedArgs& A, float* out, double* outq, const double* P, const f
         for (int k = 0; k < 3; ++k) ray[k] += std::fabs(d[k]);
     }
     A.y_fastest = ray[1] > ray[0] ? 1 : 0;
+    set_tiles(A, N);
     // The kernels take the matrices in the batch's ray frame: column 0
     // multiplies the transverse coordinate, column 1 the one along the
     // rays (the workgroup order's fastest axis).  With rays along x, swap.
@@ -490,6 +498,7 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
         A.m = mats + 12 * (size_t)v0;
         A.mq = matsq + 12 * (size_t)v0;
         A.y_fastest = B.y_fastest[b];
+        set_tiles(A, N);
         hipEvent_t t0;
         if ((rc = timed_begin(stream, &t0)) != FDK_OK) return rc;
         e = launch_fused(A, dtype, layout, B.wcheck[b] != 0, g_rows_free && B.rows_free[b] != 0,
@@ -713,6 +722,7 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
         A.m = mats + 12 * (size_t)v0;
         A.mq = matsq + 12 * (size_t)v0;
         A.y_fastest = B.y_fastest[b];
+        set_tiles(A, N);
         const bool wcheck = B.wcheck[b] != 0;
         A.fp_rmax2 = wcheck ? 0.0f : batch_rmax2(host_q + 12 * (size_t)v0, cnt, N);
         hipEvent_t t0;

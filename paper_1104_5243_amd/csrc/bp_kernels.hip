@@ -459,8 +459,8 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     // index is uniform: read it into a scalar register)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wx0 = tx * kTileX;
-    const int wy0 = ty * kTileY + wave * kWaveY;
+    int wx0, wy0;
+    wave_origin(A.y_fastest != 0, tx, ty, wave, wx0, wy0);
     const int x = wx0 + (lane % kWaveX);
     const int y = wy0 + (lane / kWaveX);
     const int zl0 = zc * kFusedZ;  // first z of this thread, relative to z_first

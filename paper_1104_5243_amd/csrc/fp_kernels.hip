@@ -129,8 +129,8 @@ __global__ __launch_bounds__(kThreads) void fp_scatter_kernel(const FusedArgs A)
     const int ty = A.y_fastest ? t0 : t1;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wx0 = tx * kTileX;
-    const int wy0 = ty * kTileY + wave * kWaveY;
+    int wx0, wy0;
+    wave_origin(A.y_fastest != 0, tx, ty, wave, wx0, wy0);
     const int x = wx0 + (lane % kWaveX);
     const int y = wy0 + (lane / kWaveX);
     const int zl0 = zc * kFpZ;
