@@ -274,7 +274,10 @@ int fdk_update_probe(float* a, size_t n, float s, void* stream);
  * projection, pre-filter and row-convolution kernels is bracketed by HIP
  * events on its stream; fdk_profile_end() waits for them and returns the
  * summed kernel milliseconds and the launch count, then stops timing.
- * Per thread of the caller; not for use across threads.
+ * Process-wide: launches from every host thread between the two calls
+ * count (a training framework may run the backward pass on a thread of its
+ * own).  Launches enqueued while fdk_profile_begin or fdk_profile_end runs
+ * on another thread may or may not be counted.
  */
 int fdk_profile_begin(void);
 int fdk_profile_end(double* kernel_ms, int* launches);

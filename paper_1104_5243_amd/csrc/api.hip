@@ -43,12 +43,14 @@ int hip_fail(hipError_t e, const char* what)
 // ---- staging buffer (one per device; Staging is declared in api_internal.h) ----
 std::mutex g_stage_mu;
 std::unordered_map<int, Staging> g_stage;
-// ---- kernel timing (per calling thread) ----------------------------------
+// ---- kernel timing (process-wide: launches from every thread count, e.g.
+// a framework's backward pass running on a worker thread) ----------------
 struct Timing {
-    bool on = false;
+    std::atomic<bool> on{false};
+    std::mutex mu;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
 };
-thread_local Timing g_timing;
+Timing g_timing;
 
 int timed_begin(hipStream_t s, hipEvent_t* e0)
 {
@@ -61,11 +63,15 @@ int timed_begin(hipStream_t s, hipEvent_t* e0)
 
 int timed_end(hipStream_t s, hipEvent_t e0)
 {
-    if (!g_timing.on || !e0) return FDK_OK;
+    if (!e0) return FDK_OK;
     hipEvent_t e1;
     hipError_t e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e != hipSuccess) return hip_fail(e, "timing event");
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "timing event");
+    }
+    std::lock_guard<std::mutex> lock(g_timing.mu);
     g_timing.ev.emplace_back(e0, e1);
     return FDK_OK;
 }
@@ -618,26 +624,30 @@ int run_fused_noalloc(float* volume, int N, float voxel_size, const float* origi
 }
 
 // LDS tile of the forward projection: the largest detector footprint (with
-// the kernel's margins) of a 16^3 workgroup box at the volume's corners or
-// centre over the batch's views, rounded up to a power of two in
-// [8192, 32768] entries (32-128 KiB).  Boxes with a larger footprint fall
-// back to global atomics in the kernel.
+// the kernel's margins) of a workgroup box (16 voxels across the rays, 32
+// along them, 16 in z; `mats` are in the batch's ray frame) at the volume's
+// corners or centre over the batch's views, rounded up to a multiple of 512
+// in [8192, 32768] entries (32-128 KiB).  Boxes with a larger footprint
+// fall back to global atomics in the kernel.  (Sized to the footprint
+// rather than to a power of two: fdk256x8's 8547 entries fit 36 KiB, and
+// three workgroups a CU, instead of 64 KiB and two.)
 int fp_tile_entries(const float* mats, int cnt, int N)
 {
     const double c = 0.5 * (N - 1);
-    const double e = std::min(15.0, (double)(N - 1));
+    const double e = std::min(15.0, (double)(N - 1));   // across the rays and in z
+    const double er = std::min(31.0, (double)(N - 1));  // along the rays
     double worst = 0.0;
     for (int j = 0; j < cnt; ++j) {
         const float* q = mats + 12 * (size_t)j;
         for (int b = 0; b < 9; ++b) {
             // box origin: a volume corner (b < 8) or the centre
             const double bx = b == 8 ? -0.5 * e : ((b & 1) ? c - e : -c);
-            const double by = b == 8 ? -0.5 * e : ((b & 2) ? c - e : -c);
+            const double by = b == 8 ? -0.5 * er : ((b & 2) ? c - er : -c);
             const double bz = b == 8 ? -0.5 * e : ((b & 4) ? c - e : -c);
             double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
             bool ok = true;
             for (int k = 0; k < 8; ++k) {
-                const double x = bx + ((k & 1) ? e : 0), y = by + ((k & 2) ? e : 0),
+                const double x = bx + ((k & 1) ? e : 0), y = by + ((k & 2) ? er : 0),
                              z = bz + ((k & 4) ? e : 0);
                 const double w = q[8] * x + q[9] * y + q[10] * z + q[11];
                 if (!(w > 0.0)) ok = false;
@@ -654,9 +664,7 @@ int fp_tile_entries(const float* mats, int cnt, int N)
             worst = std::max(worst, area);
         }
     }
-    int cap = 8192;
-    while (cap < 32768 && cap < worst) cap <<= 1;
-    return cap;
+    return (int)std::min(32768.0, std::max(8192.0, std::ceil(worst / 512.0) * 512.0));
 }
 
 // The largest 1/w^2 over the centred box [-c, c]^3 (w is affine: its
@@ -730,10 +738,10 @@ int run_forward(float* proj, int n_views, int H, int W, const double* P, const f
         if (wcheck || !g_fp_lds) {
             e = launch_scatter(A, wcheck, stream);
         } else {
-            FusedArgs C = A;  // 16 x 16 column tiles
+            FusedArgs C = A;  // column tiles of 16 across the rays x 32 along them
             C.fp_tile = fp_tile_entries(st->host_mats + 12 * (size_t)v0, cnt, N);
-            C.tiles_x = (N + 15) / 16;
-            C.tiles_y = (N + 15) / 16;
+            C.tiles_x = C.y_fastest ? (N + 15) / 16 : (N + 31) / 32;
+            C.tiles_y = C.y_fastest ? (N + 31) / 32 : (N + 15) / 16;
             const long long blocks = (long long)C.tiles_x * C.tiles_y * C.zchunks;
             C.xcd_remap = (blocks % 8 == 0) ? 1 : 0;
             // each box's views split over up to 4 workgroups of >= 16 views:
@@ -900,6 +908,7 @@ int fdk_update_probe(float* a, size_t n, float s, void* stream)
 int fdk_profile_begin(void)
 {
     g_err.clear();
+    std::lock_guard<std::mutex> lock(g_timing.mu);
     for (auto& p : g_timing.ev) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
@@ -914,6 +923,7 @@ int fdk_profile_end(double* kernel_ms, int* launches)
     g_err.clear();
     double total = 0.0;
     int rc = FDK_OK;
+    std::lock_guard<std::mutex> lock(g_timing.mu);
     for (auto& p : g_timing.ev) {
         float ms = 0.0f;
         hipError_t e = hipEventSynchronize(p.second);

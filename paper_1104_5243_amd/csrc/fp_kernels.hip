@@ -227,8 +227,9 @@ hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
 // ---------------------------------------------------------------------------
 // LDS tiles
 // ---------------------------------------------------------------------------
-// A workgroup owns a 16 x 16 x 16 voxel box: 2 x 2 of the backprojection's
-// 8 x 8 x 16 boxes.  Per view the boxes' projected intervals bound the
+// A workgroup owns a box of 16 voxels across the rays, 32 along them and 16
+// in z: 2 x 4 of the backprojection's 8 x 8 x 16 boxes.  Per view the
+// boxes' projected intervals bound the
 // workgroup's footprint on the detector; the workgroup accumulates its
 // scatter into an LDS tile covering that footprint (plus a 1-pixel margin)
 // and then adds the tile's non-zero pixels to the padded plane with one
@@ -238,15 +239,18 @@ hipError_t launch_scatter(const FusedArgs& a, bool wcheck, hipStream_t s)
 //
 // The tile accumulates in 32-bit fixed point with integer LDS atomics
 // (float LDS atomics measured ~40x slower than integer ones on this GPU).
-// Per view the tile's scale is a power of two St with 4096 * max|x| * max r^2
+// Per view the tile's scale is a power of two St with 8192 * max|x| * max r^2
 // * St below 2^31, where max|x| is the largest voxel value of the workgroup's
 // box and max r^2 = 1 / (min w)^2 over it: a pixel receives at most one tap
-// of each of the box's 4096 voxels and each tap is at most |x| r^2, so no
+// of each of the box's 8192 voxels and each tap is at most |x| r^2, so no
 // tile sum can overflow.  Each tap is rounded to the nearest multiple of
 // 1/St; a tile sum is then exact, and its conversion to the plane's scale
 // (a shift) is exact or rounds once.
-constexpr int kFpTile = 16;
-constexpr int kFpChunk = 16;  // views whose anchors are computed together
+constexpr int kFpTile = 16;                // voxels across the rays and in z
+constexpr int kFpRayBoxes = 4;             // backprojection boxes along the ray
+constexpr int kFpRay = 8 * kFpRayBoxes;    // voxels per thread along the ray
+constexpr int kFpBoxes = 2 * kFpRayBoxes;  // backprojection boxes per workgroup
+constexpr int kFpChunk = 64 / kFpBoxes;    // views whose anchors are computed together
 
 // waves per SIMD the registers are fitted to (up to 128 VGPRs)
 #ifndef FDK_FP_WAVES
@@ -270,15 +274,24 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     extern __shared__ int tile[];  // A.fp_tile entries
     // anchors (16 words) and projected bounds (8 words) of the 4 boxes for a
     // chunk of views, and the waves' largest |x|
-    __shared__ float rows[4][kFpChunk][16];
-    __shared__ float bnds[4][kFpChunk][8];
+    __shared__ float rows[kFpBoxes][kFpChunk][16];
+    __shared__ float bnds[kFpBoxes][kFpChunk][8];
     __shared__ float wave_max[4];
+    // The backprojection's workgroup order (ray axis, then z, then across),
+    // dealt to the XCDs one ray line of G boxes at a time: the launch's
+    // workgroups go to the 8 XCDs in turn, and XCD x takes lines x, x + 8,
+    // x + 16, ...  Boxes along a ray project onto the same pixels, so a line
+    // keeps its plane traffic in one L2, while lines spread over the whole
+    // volume even out the XCDs' work: only the boxes that hold some of the
+    // volume's mass work, and contiguous slabs per XCD (the backprojection's
+    // mapping) gave them 0 to 240 of fdk256x8's 949 working boxes.
+    // (fdk256x8: 2.75 against 3.07 ms of kernel time per projection.)
     int bid = blockIdx.x;
-    if (A.xcd_remap) {
-        const int per = gridDim.x >> 3;
-        bid = (bid & 7) * per + (bid >> 3);
+    const int G = A.y_fastest ? A.tiles_y : A.tiles_x;
+    if (A.xcd_remap && gridDim.x % (8 * G) == 0) {  // (whole groups of 8 lines)
+        const int k = bid >> 3, xcd = bid & 7;
+        bid = ((k / G) * 8 + xcd) * G + k % G;
     }
-    // the backprojection's workgroup order: ray axis, then z, then across
     const int t0 = bid % (A.y_fastest ? A.tiles_y : A.tiles_x);
     const int rest = bid / (A.y_fastest ? A.tiles_y : A.tiles_x);
     const int zc = rest % A.zchunks;
@@ -287,20 +300,24 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     const int ty = A.y_fastest ? t0 : t1;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int bx0 = tx * kFpTile, by0 = ty * kFpTile;
+    const int bx0 = tx * (ALONG_Y ? kFpTile : kFpRay), by0 = ty * (ALONG_Y ? kFpRay : kFpTile);
     const int zl0 = zc * kFpZ, zs0 = A.z_first + zl0;
-    // A thread owns the 16 voxels of the box along the axis closest to the
+    // A thread owns the 32 voxels of the box along the axis closest to the
     // batch's rays (y if ALONG_Y, else x); the lanes of a wave span the
     // other horizontal axis (16) and 4 slices.  Voxels along a ray project
     // onto the same pixels: this way they fall to one thread, one after the
     // other, and the 64 lanes of an atomic instruction hit 64 distinct
     // places (transverse neighbours ~2 px apart, z neighbours ~2 rows).
+    // The same reason makes the box long along the rays: a 16 x 32 x 16 box
+    // covers ~1.5 times the pixels of a 16 x 16 x 16 one, so a flushed
+    // pixel carries more voxels' taps (fdk256x8: 7.15 against 10.0 ms per
+    // projection of a dense volume, 2.23 against 2.77 ms of the phantom).
     const int tt = threadIdx.x & 15, zz = threadIdx.x >> 4;
     const int x = ALONG_Y ? bx0 + tt : bx0;  // first voxel of the thread's line
     const int y = ALONG_Y ? by0 : by0 + tt;
     const int z = zs0 + zz;
 
-    float val[kFpTile];
+    float val[kFpRay];
     const size_t slice = (size_t)A.N * A.N;
     const bool zin = zl0 + zz < A.nz;
     // every lane reads an existing voxel (indices clamped into the volume)
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     const float* src = A.vol + (size_t)min(z, A.z_first + A.nz - 1) * slice;
     float vmax = 0.0f;
 #pragma unroll
-    for (int i = 0; i < kFpTile; ++i) {
+    for (int i = 0; i < kFpRay; ++i) {
         const int xi = ALONG_Y ? x : x + i, yi = ALONG_Y ? y + i : y;
         const float v = src[(size_t)min(yi, A.N - 1) * A.N + min(xi, A.N - 1)];
         val[i] = (zin && xi < A.N && yi < A.N) ? v : 0.0f;
@@ -323,15 +340,14 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     if (vmax == 0.0f) return;  // nothing to project (uniform over the block)
     for (int e = threadIdx.x; e < A.fp_tile; e += 256) tile[e] = 0;
 
-    // the thread's two boxes along its line (b = bx + 2 by) and its offsets
+    // the thread's boxes along its line (box b = bt + 2 br: bt across the
+    // rays, br along them) and its offsets
     const int tb = tt >> 3;
-    int box[2];
-    float d_t[2], h_r[2];
+    float d_t[kFpRayBoxes], h_r[kFpRayBoxes];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        box[h] = ALONG_Y ? (tb + 2 * h) : (h + 2 * tb);
-        const BoxFrame f = box_frame(A, bx0 + 8 * (box[h] & 1), by0 + 8 * (box[h] >> 1), zs0,
-                                     kWaveX, kWaveY, kFpZ);
+    for (int h = 0; h < kFpRayBoxes; ++h) {
+        const int ox = ALONG_Y ? 8 * tb : 8 * h, oy = ALONG_Y ? 8 * h : 8 * tb;
+        const BoxFrame f = box_frame(A, bx0 + ox, by0 + oy, zs0, kWaveX, kWaveY, kFpZ);
         d_t[h] = (float)(tt & 7) - (ALONG_Y ? f.hx : f.hy);
         h_r[h] = ALONG_Y ? f.hy : f.hx;
     }
@@ -345,11 +361,12 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
     const int jbeg = blockIdx.y * per, jend = min(A.count, jbeg + per);
     unsigned long long* plane = A.acc64 + (size_t)jbeg * A.plane;
     for (int j0 = jbeg; j0 < jend; j0 += kFpChunk, plane += kFpChunk * A.plane) {
-        if (threadIdx.x < 4 * kFpChunk) {
+        if (threadIdx.x < kFpBoxes * kFpChunk) {
             // thread (b, view): the anchor of box b for view j0 + view
             const int b = threadIdx.x / kFpChunk, jv = threadIdx.x % kFpChunk;
-            const BoxFrame f = box_frame(A, bx0 + 8 * (b & 1), by0 + 8 * (b >> 1), zs0, kWaveX,
-                                         kWaveY, kFpZ);
+            const int ox = ALONG_Y ? 8 * (b & 1) : 8 * (b >> 1);
+            const int oy = ALONG_Y ? 8 * (b >> 1) : 8 * (b & 1);
+            const BoxFrame f = box_frame(A, bx0 + ox, by0 + oy, zs0, kWaveX, kWaveY, kFpZ);
             const Anchor an = make_anchor<true>(A, j0 + jv, f);
             float* row = rows[b][jv];
             *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
@@ -373,7 +390,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
             float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmx = -INFINITY;
             float wmin = INFINITY, parts = 0.0f;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < kFpBoxes; ++b) {
                 const float4 q0 = *(const float4*)bnds[b][jj];
                 const float4 q1 = *(const float4*)(bnds[b][jj] + 4);
                 umin = fminf(umin, q0.x);
@@ -394,7 +411,7 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
             const int V1 = finite ? min((int)floorf(uniform_f(vmx)) + 2, A.hi_iv + 1) : 0;
             const int TW = U1 - U0 + 1, TH = V1 - V0 + 1;
             const float rmax = 1.0f / uniform_f(wmin);
-            const float bound = 4096.0f * vmax * rmax * rmax;
+            const float bound = (float)(256 * kFpRay) * vmax * rmax * rmax;
             const bool use_lds = finite && TW * TH <= A.fp_tile && bound >= 1e-20f &&
                                  bound <= 1e30f;
             const int kt =
@@ -402,11 +419,12 @@ __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedAr
             const float St = __builtin_ldexpf(1.0f, kt);
             const const_float* m = mats + 12 * (j0 + jj);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < kFpRayBoxes; ++h) {
                 // a box whose every tap is off the detector scatters nothing
                 // (the backprojection skips it: its taps read zeros)
-                if (bnds[box[h]][jj][5] == 0.0f) continue;
-                const float* row = rows[box[h]][jj];
+                const int bh = tb + 2 * h;
+                if (bnds[bh][jj][5] == 0.0f) continue;
+                const float* row = rows[bh][jj];
                 const float4 r0 = *(const float4*)row;
                 const float4 r1 = *(const float4*)(row + 4);
                 const float4 r2 = *(const float4*)(row + 8);
