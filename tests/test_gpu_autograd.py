@@ -102,8 +102,11 @@ def test_forward_projector_matches_oracle_transpose(env):
 
 
 def test_forward_projector_accumulates_and_handles_ragged_grids(env):
+    """Volumes smaller than one workgroup box, and 70^3: two whole boxes of
+    32 voxels along the rays and a ragged third (6), ragged in z and across
+    the rays too."""
     torch, fdk, ag, dev, geom = env
-    for N in (1, 7, 19):
+    for N in (1, 7, 19, 70):
         vs = 150.0 / N
         o = (-75.0 + vs / 2 + 1.0, -75.0 + vs / 2, -75.0 + vs / 2 - 2.0)
         rng = np.random.default_rng(N)
