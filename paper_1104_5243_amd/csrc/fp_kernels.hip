@@ -272,7 +272,7 @@ template <bool ALONG_Y>
 __global__ __launch_bounds__(256, FDK_FP_WAVES) void fp_lds_kernel(const FusedArgs A)
 {
     extern __shared__ int tile[];  // A.fp_tile entries
-    // anchors (16 words) and projected bounds (8 words) of the 4 boxes for a
+    // anchors (16 words) and projected bounds (8 words) of the 8 boxes for a
     // chunk of views, and the waves' largest |x|
     __shared__ float rows[kFpBoxes][kFpChunk][16];
     __shared__ float bnds[kFpBoxes][kFpChunk][8];
