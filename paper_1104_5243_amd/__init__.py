@@ -402,7 +402,8 @@ def profile_begin():
 
 
 def profile_end():
-    """(summed backprojection-kernel milliseconds, number of launches)."""
+    """(summed milliseconds of the library's timed kernels, number of
+    launches), over every host thread since profile_begin()."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_int(0)
     _check(lib().fdk_profile_end(ctypes.byref(ms), ctypes.byref(n)))

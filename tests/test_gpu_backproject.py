@@ -247,6 +247,38 @@ def test_ragged_grids(torch_dev, fdk_mod, stack, N):
     assert oracle.rel_rmse(got, ref) <= tol(67)
 
 
+def test_kernel_timing_counts_every_thread(torch_dev, fdk_mod, stack):
+    """fdk_profile_begin/end count the launches of every host thread (a
+    framework may run a backward pass on a worker thread): one call on this
+    thread and one on another, 67 views each at the default 64-view pass,
+    give four timed launches."""
+    import threading
+    torch, dev = torch_dev
+    geom, proj, proj_d = stack
+    vs, o = synth.volume_frame(16)
+    vol = torch.zeros(16, 16, 16, device=dev)
+    fdk_mod.backproject(vol, proj_d[:67], geom.P[:67], vs, o)  # (staging allocated)
+    torch.cuda.synchronize()
+    fdk_mod.profile_begin()
+    fdk_mod.backproject(vol, proj_d[:67], geom.P[:67], vs, o)
+    torch.cuda.synchronize()
+    errors = []
+
+    def other():
+        try:
+            fdk_mod.backproject(vol, proj_d[:67], geom.P[:67], vs, o)
+            torch.cuda.synchronize()
+        except Exception as e:  # reported below, on the test's thread
+            errors.append(e)
+
+    th = threading.Thread(target=other)
+    th.start()
+    th.join()
+    ms, n = fdk_mod.profile_end()
+    assert not errors
+    assert n == 4 and ms > 0.0
+
+
 def test_zero_views_leaves_volume_unchanged(torch_dev, fdk_mod, stack):
     torch, dev = torch_dev
     geom, proj, proj_d = stack
