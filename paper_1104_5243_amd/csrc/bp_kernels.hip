@@ -436,28 +436,29 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     constexpr uint32_t kElem = sizeof(E) * layout_width(LAYOUT);
     constexpr int kFusedZ = fused_z(TT::id);
     // The launch's workgroups go to the 8 XCDs in turn (workgroup i to XCD
-    // i mod 8); each XCD takes whole slabs of the workgroup order below, so
-    // that the views' footprints of a slab share its L2.  Slabs at the
-    // volume's edges across the rays execute fewer (box, view) pairs (more
-    // of their boxes miss the detector), so with 16 groups of slabs across
-    // the rays XCD x takes groups x and x + 8, an outer one with an inner
-    // one (fdk512 FP32: 32.6 against 32.95 ms per backprojection with one
-    // contiguous eighth of the order per XCD; bit-identical).
+    // i mod 8); each XCD takes whole transverse tiles of the workgroup order
+    // below (slabs one tile thick across the rays), so that the views'
+    // footprints of a slab share its L2.  The slabs at the volume's edges
+    // across the rays execute fewer (box, view) pairs (more of their boxes
+    // miss the detector), so XCD x takes tiles x, x + 8, x + 16, ..., spread
+    // from the edges to the centre, rather than one contiguous eighth of the
+    // order (fdk512 FP32: 2014.6 -> 2062.3 GUP/s, fdk1024: 211 -> 205 ms per
+    // backprojection; bit-identical).
     int bid = blockIdx.x;
     if (A.xcd_remap) {
-        const int per = gridDim.x >> 3, xcd = bid & 7, k = bid >> 3;
+        const int xcd = bid & 7, k = bid >> 3;
         const int across = A.y_fastest ? A.tiles_x : A.tiles_y;
-        if (across % 16 == 0) {
-            const int half = (across / 16) * (gridDim.x / across);  // workgroups of a group
-            bid = k < half ? xcd * half + k : (xcd + 8) * half + (k - half);
+        if (across % 8 == 0) {
+            const int slab = gridDim.x / across;  // workgroups of one transverse tile
+            bid = (xcd + 8 * (k / slab)) * slab + k % slab;
         } else {
-            bid = xcd * per + k;
+            bid = xcd * (gridDim.x >> 3) + k;
         }
     }
     // Workgroup order: the tile axis closest to the batch's rays fastest,
     // then the z chunks, then the transverse axis.  With the XCD remap an
-    // XCD gets contiguous ranges of this order: slabs a tile or two thick
-    // across the rays, spanning the whole ray extent and all z, whose
+    // XCD gets contiguous ranges of this order: slabs a tile thick across
+    // the rays, spanning the whole ray extent and all z, whose
     // projection is a narrow band of detector columns, and the workgroups
     // resident on it at one time form a compact box along the rays.
     // (Measured on fdk512 FP32: 40.8 ms per backprojection with the z chunks
