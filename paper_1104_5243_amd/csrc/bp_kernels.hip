@@ -471,13 +471,23 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     const int ty = A.y_fastest ? t0 : t1;
 
     // each 64-lane wave covers a kWaveX x kWaveY patch of columns (the wave
-    // index is uniform: read it into a scalar register)
+    // index is uniform: read it into a scalar register).  Lanes are laid out
+    // in the batch's ray frame: consecutive lanes step across the rays, and
+    // lanes 8 apart along them.  Columns along a ray project onto nearly the
+    // same pixel, so every gather's eight pixels are each read by eight
+    // lanes 8 apart; with the lanes in x/y order, batches whose rays run
+    // along x had those eight lanes consecutive instead, and their launches
+    // took ~15 % longer (fdk512 FP32: 32.0 -> 29.9 ms per backprojection,
+    // FP16 28.2 -> 25.6 ms; bit-identical).
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int wx0, wy0;
     wave_origin(A.y_fastest != 0, tx, ty, wave, wx0, wy0);
-    const int x = wx0 + (lane % kWaveX);
-    const int y = wy0 + (lane / kWaveX);
+    static_assert(kWaveX == kWaveY, "a square wave patch (either axis may run across the rays)");
+    const int lx = A.y_fastest ? (lane % kWaveX) : (lane / kWaveX);
+    const int ly = A.y_fastest ? (lane / kWaveX) : (lane % kWaveX);
+    const int x = wx0 + lx;
+    const int y = wy0 + ly;
     const int zl0 = zc * kFusedZ;  // first z of this thread, relative to z_first
     // the part of this wave's box inside the volume (kept in scalar
     // registers) and this thread's offsets from its centre column
@@ -488,8 +498,8 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     bf.hx = uniform_f(bf.hx);
     bf.hy = uniform_f(bf.hy);
     bf.hz = uniform_f(bf.hz);
-    const float dx = (float)(lane % kWaveX) - bf.hx;
-    const float dy = (float)(lane / kWaveX) - bf.hy;
+    const float dx = (float)lx - bf.hx;
+    const float dy = (float)ly - bf.hy;
     const float d_t = A.y_fastest ? dx : dy;  // transverse and ray offsets
     const float d_r = A.y_fastest ? dy : dx;
 
