@@ -559,9 +559,23 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
         __syncthreads();  // every wave has read its rows before the next chunk's
     }
 
-    if (x < A.N && y < A.N) {
+    // With the rays along x, lane (a, b) holds column (x0 + b, y0 + a):
+    // transpose the wave's 8 x 8 patch through the lane crossbar so that
+    // consecutive lanes read and write consecutive x in the volume (fdk512:
+    // FP32 29.5 -> 29.2 ms per backprojection, FP16 25.3 -> 25.0 ms).
+    int ex = x, ey = y;
+    if (!A.y_fastest) {
+        const int src = ((lane & 7) << 3) | (lane >> 3);  // the lane holding (x0 + lane % 8, y0 + lane / 8)
+#pragma unroll
+        for (int i = 0; i < kFusedZ; ++i)
+            acc[i] = __builtin_bit_cast(
+                float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, acc[i])));
+        ex = wx0 + (lane & 7);
+        ey = wy0 + (lane >> 3);
+    }
+    if (ex < A.N && ey < A.N) {
         const size_t slice = (size_t)A.N * A.N;
-        float* out = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)y * A.N + x;
+        float* out = A.vol + (size_t)(A.z_first + zl0) * slice + (size_t)ey * A.N + ex;
         if (zl0 + kFusedZ <= A.nz) {
             // all the column's loads in flight together (a test per voxel
             // would make the compiler wait for each before the next)
