@@ -29,9 +29,17 @@
  *     until the stream has passed the call.  Two calls that write the same
  *     output must be ordered on one stream (or by events) by the caller.
  *   - The library never frees or retains caller memory.  It owns one
- *     staging buffer per device (zero-padded copies of a batch of views),
- *     grown on demand and released by fdk_release().  Calls on different
- *     streams that share it are ordered by the library with events.
+ *     staging buffer per device (zero-padded copies of a batch of views;
+ *     two batches when a call of the fused kernel with FP16 or BF16 views
+ *     has several, so that the next batch is staged on a second stream of
+ *     the library's while the current one is backprojected), grown on
+ *     demand and released by fdk_release().  The second stream starts after
+ *     the caller's earlier work on `stream`, and the call's last kernel, on
+ *     `stream`, follows all of its work, so the call is ordered on `stream`
+ *     as a whole.  Calls on different streams that share the buffer are
+ *     ordered by the library with events.  (FDK_STAGE_OVERLAP=0 or 1 in the
+ *     environment at load time stages on `stream` itself, or on the second
+ *     stream, for every storage type.)
  * Errors: every entry point returns FDK_OK (0) or a negative code, and
  * fdk_last_error() describes the last failure of the calling thread.
  * Arguments are validated before anything is enqueued; a rejected call has
@@ -283,8 +291,9 @@ int fdk_profile_begin(void);
 int fdk_profile_end(double* kernel_ms, int* launches);
 
 /* Views per launch of the fused backprojection and the forward projection
-   (1..1024, default 64; the staging buffer holds that many views, up to
-   8 GiB); 0 reads it back.  The plain kernel takes at most 64 per launch. */
+   (1..1024, default 64; the staging buffer holds that many views, or twice
+   as many when a call stages on the second stream, up to 8 GiB per batch);
+   0 reads it back.  The plain kernel takes at most 64 per launch. */
 int fdk_set_batch(int views_per_pass);
 
 /*

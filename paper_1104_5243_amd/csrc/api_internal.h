@@ -28,6 +28,13 @@ struct Staging {
     float* host_mats = nullptr;
     size_t host_floats = 0;
     hipEvent_t mats_copied = nullptr;  // recorded after the last such copy
+    // the fused backprojection's second stream, on which the next pass's
+    // views are staged into the other half of the buffer while the current
+    // pass runs (default priority, non-blocking; created on first use)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr;                // the call's start, on its stream
+    hipEvent_t staged[2] = {nullptr, nullptr};  // a half filled (side stream)
+    hipEvent_t freed[2] = {nullptr, nullptr};   // a half's pass done (call's stream)
 };
 extern std::mutex g_stage_mu;
 // The calling device's staging buffer with at least `bytes`, `stream`

@@ -234,6 +234,48 @@ def test_batch_size_does_not_change_result(torch_dev, fdk_mod, stack, ref128, ba
     assert err <= tol(67)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("batch", [16, 64])
+def test_call_is_ordered_on_the_callers_stream(torch_dev, fdk_mod, stack, batch, storage):
+    """With several passes of 16-bit views the library stages the next
+    pass's views on a second stream of its own.  The views are written on
+    the caller's stream behind ~10 ms of other work just before the call,
+    and the volume is read on that stream just after it: the result must
+    equal the one from views already in place (the side stream waits for
+    the caller's earlier work, and the call's end on the caller's stream
+    waits for the side stream)."""
+    torch, dev = torch_dev
+    geom, proj, proj_d = stack
+    vs, o = synth.volume_frame(128)
+    P = geom.P[:150]
+    views, scale = proj_d[:150], None
+    if storage == "f16":
+        views, scale = fdk_mod.to_storage(views, torch.float16)
+    old = fdk_mod.set_batch(0)
+    try:
+        fdk_mod.set_batch(batch)
+        want = torch.zeros(128, 128, 128, device=dev)
+        fdk_mod.backproject(want, views, P, vs, o, view_scale=scale)
+        late = torch.zeros_like(views)
+        vol = torch.zeros(128, 128, 128, device=dev)
+        a = torch.randn(4096, 4096, device=dev)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(s):
+            for _ in range(8):
+                torch.mm(a, a, out=c)
+            late.copy_(views)
+            fdk_mod.backproject(vol, late, P, vs, o, view_scale=scale, stream=s)
+            got = vol.clone()
+        torch.cuda.synchronize()
+    finally:
+        fdk_mod.set_batch(old)
+    print(f"{storage} batch {batch}: nonzero {int((want != 0).sum())}", flush=True)
+    assert torch.any(want != 0)
+    assert torch.equal(got, want)
+
+
 @pytest.mark.parametrize("N", [1, 2, 17, 37])
 def test_ragged_grids(torch_dev, fdk_mod, stack, N):
     """Grids that are not a multiple of the 16x16x16 thread tile, with 67
