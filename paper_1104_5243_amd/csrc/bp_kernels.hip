@@ -363,8 +363,12 @@ static_assert(fused_z(kF32) % kGroup == 0 && fused_z(kF16) % kGroup == 0,
 // anchored indices); with VCLAMP false only u is clamped, and a tap row
 // outside the plane gives a byte offset outside the buffer's range, which
 // reads as zero (the host has bounded the rows so that the offset cannot
-// wrap into the plane).
-template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV>
+// wrap into the plane).  With CLAMP false nothing is clamped: for a box
+// whose projected hull lies a pixel inside the clamp ranges, where every
+// clamp of a voxel inside the volume is a no-op (lanes of voxels beyond the
+// volume's edge may then read anywhere: their loads stay within the plane's
+// range-checked buffer and their sums are never written).
+template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV, bool CLAMP = true>
 __device__ __forceinline__ void accumulate_view(
     const FusedArgs& A, float uc, float vc, float wc, float su_t, float su_r, float su2,
     float sv_t, float sv_r, float sv2, float sw_t, float sw_r, float sw2, int lo_u, int hi_u,
@@ -393,8 +397,8 @@ __device__ __forceinline__ void accumulate_view(
             // part 2
             au[q] = __builtin_amdgcn_fractf(u);
             av[q] = __builtin_amdgcn_fractf(v);
-            const int ju = med3_i32(cvt_floor(u), lo_u, hi_u);
-            const int jv = VCLAMP ? med3_i32(cvt_floor(v), lo_v, hi_v) : cvt_floor(v);
+            const int ju = CLAMP ? med3_i32(cvt_floor(u), lo_u, hi_u) : cvt_floor(u);
+            const int jv = (CLAMP && VCLAMP) ? med3_i32(cvt_floor(v), lo_v, hi_v) : cvt_floor(v);
             const uint32_t off = (uint32_t)(mad_i24_ub(jv, Wp, ju) + base) * kElem;
             if constexpr (kIsF32)
                 load_taps<LAYOUT>(TT{}, rsrc, off, row_bytes, tl[q], tr[q], bl[q], br[q]);
@@ -425,9 +429,10 @@ __device__ __forceinline__ void accumulate_view(
     }
 }
 
-// waves per SIMD the register budget is fitted to (512 VGPRs / 8 = 64)
+// waves per SIMD the register budget is fitted to (512 VGPRs / 7 = 72: with
+// the clamp-free copy of the voxel loop, 8 waves' 64 VGPRs spill inside it)
 #ifndef FDK_MIN_WAVES
-#define FDK_MIN_WAVES 8
+#define FDK_MIN_WAVES 7
 #endif
 template <typename TT, int LAYOUT, bool WCHECK, bool VCLAMP, int DIV>
 __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused_kernel(const FusedArgs A)
@@ -513,8 +518,8 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
     // vector registers only while their view is processed.  Row: uc, vc,
     // wc, the u and v slopes (transverse, ray, z), the element offset of
     // pixel (a_u + ku, a_v + kv) in a plane, the tap index clamp ranges
-    // shifted by the anchor, and the w row's z slope.  (Its x and y slopes
-    // are the folded matrix's, read as scalars.)
+    // shifted by the anchor, the w row's z slope and the clamp-free flag.
+    // (The w row's x and y slopes are the folded matrix's, read as scalars.)
     __shared__ float anchors[kWgWaves][64][16];
     float(*an_rows)[16] = anchors[wave];
     const uint32_t plane_bytes = (uint32_t)(A.plane * (long long)kElem);
@@ -527,6 +532,12 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
         {
             const Anchor an = make_anchor<!WCHECK>(A, j0 + lane, bf);
             skip = __ballot(an.skip);
+            // the box's hull a pixel inside the tap clamp ranges: the view
+            // takes the clamp-free voxel loop
+            const bool inside = !WCHECK && an.wmin > 0.0f && an.umin >= (float)(A.lo_iu + 1) &&
+                                an.umax <= (float)(A.hi_iu - 1) &&
+                                an.vmin >= (float)(A.lo_iv + 1) &&
+                                an.vmax <= (float)(A.hi_iv - 1);
             const int base = an.av * A.Wp + an.au + A.origin_off;
             float* row = an_rows[lane];
             *(float4*)row = make_float4(an.uc, an.vc, an.wc, an.su_t);
@@ -536,7 +547,8 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
                                               __builtin_bit_cast(float, A.hi_iu - an.au));
             *(float4*)(row + 12) =
                 make_float4(__builtin_bit_cast(float, A.lo_iv - an.av),
-                            __builtin_bit_cast(float, A.hi_iv - an.av), an.sw2, 0.0f);
+                            __builtin_bit_cast(float, A.hi_iv - an.av), an.sw2,
+                            __builtin_bit_cast(float, inside ? 1 : 0));
         }
         __syncthreads();
         const int jn = min(64, A.count - j0);
@@ -551,10 +563,20 @@ __global__ __launch_bounds__(kThreads, WCHECK ? 7 : FDK_MIN_WAVES) void bp_fused
             const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(plane, plane_bytes);
             // (the w row's z slope from LDS, a vector register: the slice
             // FMAs take their slice index as an inline literal)
-            accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV>(
-                A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, __builtin_bit_cast(float, r2.x),
-                m[8], m[9], r3.z, r2.z, r2.w, __builtin_bit_cast(int, r3.x),
-                __builtin_bit_cast(int, r3.y), r2.y, d_t, d_r, rsrc, acc);
+            // (fdk512 FP32: 29.5 -> 28.75 ms per backprojection with the
+            // clamp-free copy; 1024^3: 195.3 -> 196.4 ms)
+            if (!WCHECK && __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, r3.w)) != 0)
+                accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV, false>(
+                    A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                    __builtin_bit_cast(float, r2.x), m[8], m[9], r3.z, r2.z, r2.w,
+                    __builtin_bit_cast(int, r3.x), __builtin_bit_cast(int, r3.y), r2.y, d_t, d_r,
+                    rsrc, acc);
+            else
+                accumulate_view<TT, LAYOUT, WCHECK, VCLAMP, DIV>(
+                    A, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                    __builtin_bit_cast(float, r2.x), m[8], m[9], r3.z, r2.z, r2.w,
+                    __builtin_bit_cast(int, r3.x), __builtin_bit_cast(int, r3.y), r2.y, d_t, d_r,
+                    rsrc, acc);
         }
         __syncthreads();  // every wave has read its rows before the next chunk's
     }
