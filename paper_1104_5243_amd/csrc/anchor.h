@@ -37,6 +37,16 @@ __device__ __forceinline__ float uniform_f(float x)
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
 }
 
+// A wave-uniform double held in scalar registers (its two halves read from
+// the first lane).
+__device__ __forceinline__ double uniform_d(double x)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // The part of a box inside the volume, in the centred index frame (all
 // values are multiples of 1/2, exact in FP32).  x0, y0: the box's first
 // column; zs0: its first slice (absolute); the box spans kx x ky columns
@@ -84,9 +94,26 @@ struct Anchor {
 
 // The anchor of view `view` of the batch (view >= A.count: a skipped dummy)
 // for the box `f`.  ANCHOR false (batches where some voxel may have w <= 0)
-// keeps a_u = a_v = 0 and skips nothing.
+// keeps a_u = a_v = 0 and skips nothing.  `bc`: box_centre(f), or where `f`
+// is the same on every lane of the wave, uniform_box_centre(f).
+// The box's centre column, first slice and centre slice in FP64.
+struct BoxCentre {
+    double cx, cy, cz, z0;
+};
+__device__ __forceinline__ BoxCentre box_centre(const BoxFrame& f)
+{
+    return BoxCentre{f.cx, f.cy, (double)f.z0 + (double)f.hz, f.z0};
+}
+// ... the same, wave-uniform, held in scalar registers
+__device__ __forceinline__ BoxCentre uniform_box_centre(const BoxFrame& f)
+{
+    const BoxCentre c = box_centre(f);
+    return BoxCentre{uniform_d(c.cx), uniform_d(c.cy), uniform_d(c.cz), uniform_d(c.z0)};
+}
+
 template <bool ANCHOR>
-__device__ __forceinline__ Anchor make_anchor(const FusedArgs& A, int view, const BoxFrame& f)
+__device__ __forceinline__ Anchor make_anchor(const FusedArgs& A, int view, const BoxFrame& f,
+                                              const BoxCentre& bc)
 {
     Anchor a;
     const bool valid = view < A.count;
@@ -94,7 +121,7 @@ __device__ __forceinline__ Anchor make_anchor(const FusedArgs& A, int view, cons
     double Q[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) Q[k] = q[k];
-    const double cx = f.cx, cy = f.cy, cz = (double)f.z0 + (double)f.hz, z0 = f.z0;
+    const double cx = bc.cx, cy = bc.cy, cz = bc.cz, z0 = bc.z0;
     int au = 0, av = 0;
     if (ANCHOR) {
         // nearest integers to u', v' at the centre (any integer near them
@@ -170,6 +197,11 @@ __device__ __forceinline__ Anchor make_anchor(const FusedArgs& A, int view, cons
     }
     a.skip = skip;
     return a;
+}
+template <bool ANCHOR>
+__device__ __forceinline__ Anchor make_anchor(const FusedArgs& A, int view, const BoxFrame& f)
+{
+    return make_anchor<ANCHOR>(A, view, f, box_centre(f));
 }
 
 // Part 1 of a voxel from its column base (num_u, num_v, w at the box's

@@ -320,22 +320,21 @@ void setup_args(FusedArgs& A, float* volume, int N, int H, int W, int Wp, long l
     A.nz = N;
     A.z_first = 0;
     A.Wp = Wp;
-    A.lo_u = (float)(-ku - kPad);
-    A.hi_u = (float)(W - ku) + 0.5f;
-    A.lo_v = (float)(-kv - kPad);
-    A.hi_v = (float)(H - kv) + 0.5f;
     // u = u' + ku.  Zero contribution iff u <= -1 or u >= W (likewise v);
     // floor(u) stays in [-2, W] iff u in [-2, W + 1).  Margins of 0.5 pixel.
     A.skip_lo_u = (float)(-1 - ku) - 0.5f;
     A.skip_hi_u = (float)(W - ku) + 0.5f;
     A.skip_lo_v = (float)(-1 - kv) - 0.5f;
     A.skip_hi_v = (float)(H - kv) + 0.5f;
-    A.in_lo_u = (float)(-1 - ku) - 0.5f;
-    A.in_lo_v = (float)(-1 - kv) - 0.5f;
     A.lo_iu = -ku - kPad;
     A.hi_iu = W - ku;
     A.lo_iv = -kv - kPad;
     A.hi_iv = H - kv;
+    // a pixel inside the index clamp ranges: floor(u') in [lo_iu, hi_iu]
+    A.in_lo_u = (float)(A.lo_iu + 1);
+    A.in_hi_u = (float)(A.hi_iu - 1);
+    A.in_lo_v = (float)(A.lo_iv + 1);
+    A.in_hi_v = (float)(A.hi_iv - 1);
     A.origin_off = (kv + kPad) * Wp + (ku + kPad);
     A.c = 0.5f * (float)(N - 1);
     A.zchunks = (N + zdepth - 1) / zdepth;

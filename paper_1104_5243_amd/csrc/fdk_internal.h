@@ -52,13 +52,11 @@ struct FusedArgs {
     int nz;              // number of z slices written (z_first .. z_first+nz-1)
     int z_first;         // first z slice
     int Wp;              // staged row pitch (elements)
-    float lo_u, hi_u;    // clamp range of u' before the floor
-    float lo_v, hi_v;
     // per-wave tests on the projected corners of a wave's voxel box (u', v'):
     // all below skip_lo or all above skip_hi -> every tap is outside the
-    // detector; all within [in_lo, skip_hi] -> no tap leaves the zero border
+    // detector; all within [in_lo, in_hi] -> no tap index clamp can act
     float skip_lo_u, skip_hi_u, skip_lo_v, skip_hi_v;
-    float in_lo_u, in_lo_v;
+    float in_lo_u, in_hi_u, in_lo_v, in_hi_v;
     int origin_off;      // element offset of pixel (ku, kv) inside a plane
     float c;             // (N-1)/2
     int count;           // views in this batch
