@@ -487,6 +487,12 @@ int plan_fused(int dtype, int H, int W, FusedPlan* F)
     return FDK_OK;
 }
 
+int run_fused_batches(FusedArgs& A, const FusedPlan& F, Staging* st, hipStream_t stage_stream,
+                      hipStream_t stream, bool overlap, size_t planes, float* mats,
+                      const double* matsq, const double* P, const float* view_scale,
+                      const void* proj, int dtype, int n_views, int batch, int N,
+                      float voxel_size, const float* origin, int H, int W);
+
 int run_fused(float* volume, int N, float voxel_size, const float* origin, const void* proj,
               int dtype, int n_views, int H, int W, const double* P, const float* view_scale,
               hipStream_t stream)
@@ -494,9 +500,8 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
     FusedPlan F;
     int rc = plan_fused(dtype, H, W, &F);
     if (rc != FDK_OK) return rc;
-    const int Hp = F.Hp, Wp = F.Wp, layout = F.layout;
+    const int Hp = F.Hp, Wp = F.Wp;
     const size_t esz = F.esz, plane_bytes = F.plane_bytes;
-    const double vlim = F.vlim;
     int batch = g_batch;
     if ((size_t)batch * plane_bytes > kMaxStagingBytes)
         batch = (int)std::max<size_t>(1, kMaxStagingBytes / plane_bytes);
@@ -530,9 +535,34 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
         if (e != hipSuccess) return hip_fail(e, "stream fork");
         stage_stream = st->side;
     }
+    rc = run_fused_batches(A, F, st, stage_stream, stream, overlap, planes, mats, matsq, P,
+                           view_scale, proj, dtype, n_views, batch, N, voxel_size, origin, H, W);
+    hipError_t e = hipSuccess;
+    if (overlap) {
+        // join the side stream back, also after a failure part-way, so that
+        // later users of the buffer on `stream` follow every staging
+        e = hipEventRecord(st->staged[0], stage_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, st->staged[0], 0);
+        if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "stream join");
+    }
+    e = hipEventRecord(st->last_use, stream);
+    if (e != hipSuccess && rc == FDK_OK) rc = hip_fail(e, "hipEventRecord");
+    return rc;
+}
+
+// The passes of run_fused: fold and upload the matrices, then per pass
+// stage its views (on `stage_stream`) and launch the backprojection.
+int run_fused_batches(FusedArgs& A, const FusedPlan& F, Staging* st, hipStream_t stage_stream,
+                      hipStream_t stream, bool overlap, size_t planes, float* mats,
+                      const double* matsq, const double* P, const float* view_scale,
+                      const void* proj, int dtype, int n_views, int batch, int N,
+                      float voxel_size, const float* origin, int H, int W)
+{
+    const int Hp = F.Hp, Wp = F.Wp, layout = F.layout;
+    const size_t esz = F.esz;
     Batches B;
-    rc = fold_and_upload(st, mats, P, view_scale, n_views, batch, N, voxel_size, origin, H, W,
-                         vlim, stream, &B);
+    int rc = fold_and_upload(st, mats, P, view_scale, n_views, batch, N, voxel_size, origin, H,
+                             W, F.vlim, stream, &B);
     if (rc != FDK_OK) return rc;
 
     for (size_t b = 0; b < B.v0.size(); ++b) {
@@ -575,8 +605,6 @@ int run_fused(float* volume, int N, float voxel_size, const float* origin, const
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
     }
-    hipError_t e = hipEventRecord(st->last_use, stream);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     return FDK_OK;
 }
 
