@@ -173,11 +173,16 @@ __device__ __forceinline__ Anchor make_anchor(const FusedArgs& A, int view, cons
         float wmin = INFINITY;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const float ex = (k & 1) ? f.hx : -f.hx, ey = (k & 2) ? f.hy : -f.hy;
+            // (the corner's -h x s as h x -s, exactly: the box's extents stay
+            // in scalar registers)
+            const bool px = k & 1, py = k & 2;
             const float ez = (k & 4) ? 2.0f * f.hz : 0.0f;
-            const float nu = fmaf(ez, (float)S[2], fmaf(ey, su1, fmaf(ex, su0, a.uc)));
-            const float nv = fmaf(ez, (float)S[6], fmaf(ey, sv1, fmaf(ex, sv0, a.vc)));
-            const float nw = fmaf(ez, (float)S[10], fmaf(ey, sw1, fmaf(ex, sw0, a.wc)));
+            const float nu = fmaf(ez, (float)S[2], fmaf(f.hy, py ? su1 : -su1,
+                                                        fmaf(f.hx, px ? su0 : -su0, a.uc)));
+            const float nv = fmaf(ez, (float)S[6], fmaf(f.hy, py ? sv1 : -sv1,
+                                                        fmaf(f.hx, px ? sv0 : -sv0, a.vc)));
+            const float nw = fmaf(ez, (float)S[10], fmaf(f.hy, py ? sw1 : -sw1,
+                                                         fmaf(f.hx, px ? sw0 : -sw0, a.wc)));
             const float r = __builtin_amdgcn_rcpf(nw);  // (~1 ulp: far inside the margins)
             umin = fminf(umin, nu * r);
             umax = fmaxf(umax, nu * r);
